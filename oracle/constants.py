@@ -1,0 +1,175 @@
+"""Oracle constants: weight integrals, polynomial coefficients and quadrature weights.
+
+TEST INFRASTRUCTURE ONLY. This module is part of the CPU oracle of the semiclassical
+lattice Boltzmann method (Coelho & Doria, "Lattice Boltzmann method for semiclassical
+fluids"). Only the tests, the package smoke check and the benchmark's CPU-baseline leg
+may import it; the GPU product path never does.
+
+Everything here is computed in arbitrary precision with mpmath (40 significant digits)
+and returned as Python floats (or mpf when asked), directly from the paper's
+definitions:
+
+* weight functions: Fermi-Dirac electron weight, eq. (weight-func-isotherm-eq) of
+  Sec. 9.1; Hermite weight, eq. (hermite-weight-eq) of Sec. 2;
+* weight integrals I_2N: eq. (i2n-cont2) of Sec. 3 (radial form);
+* polynomial coefficients c_K, c'_K, cbar_K, Delta_2K, J_2K: the coefficient list
+  of Sec. 3 (K <= 2 only; the second-order model of Sec. 9 needs nothing higher);
+* pseudo-temperature thetabar = I_2/I_0: Sec. 9.1;
+* reference speed c_s and weights w_alpha of D2V9, D3V15, D3V19, D3V27: Sec. 8 and
+  Table 1 (lattices-tab).
+
+No blocking, caching trick or reformulation is applied beyond what those formulas say.
+"""
+from __future__ import annotations
+
+import functools
+from dataclasses import dataclass
+
+import mpmath as mp
+
+mp.mp.dps = 40
+
+#: Lattices whose weights Table 1 gives in closed form in terms of I_0, I_2, I_4 (, I_6).
+LATTICE_DIM = {"D2V9": 2, "D3V15": 3, "D3V19": 3, "D3V27": 3}
+
+
+def _omega(stats: str, theta, mu, D: int):
+    """Radial weight function omega(xi).
+
+    * "fd": eq. (weight-func-isotherm-eq), Sec. 9.1: 1 / (exp((xi^2 - mu)/theta) + 1);
+      with theta = 1/270, mu = 1 this is 1/(e^-270 e^(270 xi^2) + 1).
+    * "hermite": eq. (hermite-weight-eq), Sec. 2: (2 pi)^(-D/2) exp(-xi^2/2).
+    """
+    theta = mp.mpf(theta)
+    mu = mp.mpf(mu)
+    if stats == "fd":
+        return lambda x: 1 / (mp.exp((x * x - mu) / theta) + 1)
+    if stats == "hermite":
+        pref = (2 * mp.pi) ** (-mp.mpf(D) / 2)
+        return lambda x: pref * mp.exp(-x * x / 2)
+    raise ValueError(f"unknown statistics {stats!r}")
+
+
+def _fermi_edge_points(theta, mu):
+    """Break points for the quadrature: the FD weight drops from 1 to 0 within a few
+    theta of xi^2 = mu, so the interval is split every 5 theta across the edge
+    (xi^2 = mu - 100 theta ... mu + 200 theta)."""
+    theta = mp.mpf(theta)
+    mu = mp.mpf(mu)
+    pts = [mp.mpf(0)]
+    for k in range(-100, 201, 5):
+        x2 = mu + k * theta
+        if x2 > 0:
+            pts.append(mp.sqrt(x2))
+    return sorted(set(pts))
+
+
+@functools.lru_cache(maxsize=None)
+def weight_integral(D: int, twoN: int, stats: str = "fd", theta="1/270", mu=1.0) -> mp.mpf:
+    """I_{2N} of eq. (i2n-cont2), Sec. 3:
+
+        I_2N = pi^(D/2) / (2^(N-1) Gamma(N + D/2)) * int_0^inf omega(xi) xi^(2N+D-1) dxi.
+
+    ``twoN`` is the even order 2N. ``theta`` may be given as a float or as the string
+    "1/270" for the exact rational used by the paper's electron model.
+    """
+    if twoN % 2:
+        return mp.mpf(0)  # odd moments vanish by symmetry (Sec. 3)
+    N = twoN // 2
+    th = mp.mpf(1) / 270 if theta == "1/270" else mp.mpf(theta)
+    w = _omega(stats, th, mu, D)
+    pref = mp.pi ** (mp.mpf(D) / 2) / (mp.mpf(2) ** (N - 1) * mp.gamma(N + mp.mpf(D) / 2))
+    f = lambda x: w(x) * x ** (2 * N + D - 1)
+    if stats == "fd":
+        pts = _fermi_edge_points(th, mu)
+        val = mp.quad(f, pts) + mp.quad(f, [pts[-1], mp.inf])
+    else:
+        val = mp.quad(f, [0, 1, 3, 6, 12, mp.inf])
+    return pref * val
+
+
+@dataclass(frozen=True)
+class Coefficients:
+    """Second-order polynomial coefficients and derived quantities (Sec. 3, Sec. 9.1)."""
+
+    D: int
+    I0: mp.mpf
+    I2: mp.mpf
+    I4: mp.mpf
+    I6: mp.mpf
+    c0: mp.mpf
+    c1: mp.mpf
+    c2: mp.mpf
+    c2bar: mp.mpf
+    c2p: mp.mpf
+    J2: mp.mpf
+    Delta2: mp.mpf
+    thetabar: mp.mpf
+    cs: mp.mpf
+
+
+@functools.lru_cache(maxsize=None)
+def coefficients(D: int, stats: str = "fd", theta="1/270", mu=1.0) -> Coefficients:
+    """Coefficient list of Sec. 3 for K <= 2 and the reference speed of Sec. 8.
+
+    c_K = I_2K^(-1/2); J_2 = I_2^2/(I_4 I_0); Delta_2 = sqrt(2/((D+2) - J_2 D));
+    cbar_2 = c_2 (Delta_2 - 1)/D; c'_2 = -c_2 (I_2/I_0) Delta_2;
+    thetabar = I_2/I_0 (Sec. 9.1); c_s = sqrt(I_2/(3 I_4)) (Sec. 8, Table 1).
+    """
+    I0 = weight_integral(D, 0, stats, theta, mu)
+    I2 = weight_integral(D, 2, stats, theta, mu)
+    I4 = weight_integral(D, 4, stats, theta, mu)
+    I6 = weight_integral(D, 6, stats, theta, mu)
+    c0 = 1 / mp.sqrt(I0)
+    c1 = 1 / mp.sqrt(I2)
+    c2 = 1 / mp.sqrt(I4)
+    J2 = I2 ** 2 / (I4 * I0)
+    Delta2 = mp.sqrt(2 / ((D + 2) - J2 * D))
+    c2bar = c2 * (-1 + Delta2) / D
+    c2p = -c2 * (I2 / I0) * Delta2
+    thetabar = I2 / I0
+    cs = mp.sqrt(I2 / (3 * I4))
+    return Coefficients(D, I0, I2, I4, I6, c0, c1, c2, c2bar, c2p, J2, Delta2, thetabar, cs)
+
+
+def lattice_weights(lattice: str, stats: str = "fd", theta="1/270", mu=1.0) -> dict:
+    """Quadrature weights by shell |e|^2 (0 rest, 1 axis, 2 face diagonal, 3 body
+    diagonal) and c_s, from Sec. 8 (D2V9, D3V15) and Table 1 (D3V19, D3V27).
+
+    Returns {"w": {norm2: w}, "cs": c_s} with mpf values.
+    """
+    D = LATTICE_DIM[lattice]
+    k = coefficients(D, stats, theta, mu)
+    I0, I2, I4, I6, J2 = k.I0, k.I2, k.I4, k.I6, k.J2
+    if lattice == "D2V9":
+        w = {0: I0 * (1 - 5 * J2 / 9), 1: I0 * J2 / 9, 2: I0 * J2 / 36}
+    elif lattice == "D3V15":
+        w = {0: I0 * (1 - 7 * J2 / 9), 1: I0 * J2 / 9, 3: I0 * J2 / 72}
+    elif lattice == "D3V19":
+        w = {0: I0 * (1 - 2 * J2 / 3), 1: I0 * J2 / 18, 2: I0 * J2 / 36}
+    elif lattice == "D3V27":
+        w = {
+            0: I0 - 2 * I2 ** 2 / (3 * I4) - I6 * I2 ** 3 / (27 * I4 ** 3),
+            1: (3 * I2 ** 2 * I4 ** 2 + I6 * I2 ** 3) / (54 * I4 ** 3),
+            2: (3 * I4 ** 2 * I2 ** 2 - I6 * I2 ** 3) / (108 * I4 ** 3),
+            3: I2 ** 3 * I6 / (216 * I4 ** 3),
+        }
+    else:
+        raise ValueError(lattice)
+    return {"w": w, "cs": k.cs}
+
+
+def lattice_vectors(lattice: str):
+    """Integer lattice vectors e_alpha (Sec. 8, Table 1): all vectors of the listed
+    fully symmetric shells. Returned as a list of tuples of length D; the order is the
+    oracle's own (rest, then axis, then diagonal shells)."""
+    import itertools
+
+    D = LATTICE_DIM[lattice]
+    shells = {"D2V9": (0, 1, 2), "D3V15": (0, 1, 3), "D3V19": (0, 1, 2), "D3V27": (0, 1, 2, 3)}[lattice]
+    vecs = []
+    for n2 in shells:
+        for v in itertools.product((-1, 0, 1), repeat=D):
+            if sum(c * c for c in v) == n2:
+                vecs.append(tuple(v))
+    return vecs
