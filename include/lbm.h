@@ -1,0 +1,185 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) semiclassical lattice Boltzmann library.
+ *
+ * Method: Coelho & Doria, "Lattice Boltzmann method for semiclassical fluids". The
+ * library advances the isothermal electron model of Sec. 9.1: BGK relaxation toward
+ * the second-order Fermi-Dirac equilibrium of eq. (feq-reduced-applied-electrons-in-
+ * metals-eq), expanded in the generalised polynomials of Sec. 3 and discretised on the
+ * D2V9 (Sec. 8) or D3V19 (Table 1) quadrature; the Lorentz forcing term of Sec. 7 with
+ * the velocity-dependent acceleration a = E + xi x B; streaming on the lattice vectors
+ * e_a; halfway bounce-back on solid nodes.
+ *
+ * Conventions used by every call:
+ *   - Nodes are numbered n = x + nx*(y + ny*z); 2D grids have nz = 1.
+ *   - Velocities are in xi-units, the paper's units where the Fermi speed is 1
+ *     (xi_a = e_a / c_s). rho u = sum_a f_a xi_a, rho = sum_a f_a.
+ *   - E and B are given in xi-units per time step (Delta t = 1): the field adds
+ *     rho E to rho u per step and B rotates u by |B| radians per step. In 2D only
+ *     E_x, E_y and B_z may be non-zero.
+ *   - Every device pointer is borrowed: the library owns no device memory. The caller
+ *     allocates state and work buffers of the sizes lbm_buffer_sizes reports and keeps
+ *     them (and the mask and s arrays) alive while the handle exists.
+ *   - All device work is enqueued on the HIP stream given to lbm_create; only
+ *     lbm_current synchronises. A handle is not thread-safe.
+ *   - Status codes: LBM_OK (0) or a negative LBM_E* value; no C++ exception crosses
+ *     the ABI. lbm_last_error gives a message for the last failing call on a handle.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_s *lbm_t;
+
+/* Lattices (Sec. 8, Table 1). D3V15 is listed only so that it can be rejected: under
+ * the electron weight its rest weight is negative, which Sec. 8 forbids. */
+enum { LBM_D2V9 = 0, LBM_D3V19 = 1, LBM_D3V15 = 2 };
+
+/* Weight functions: the Fermi-Dirac electron weight 1/(exp((xi^2 - mu)/theta) + 1) of
+ * eq. (weight-func-isotherm-eq), Sec. 9.1, or the Hermite weight of eq.
+ * (hermite-weight-eq), Sec. 2 (theta and mu ignored), which yields textbook D2Q9/D3Q19. */
+enum { LBM_FERMI_DIRAC = 0, LBM_HERMITE = 2 };
+
+/* Population storage. All arithmetic is FP32; storage holds deviations
+ * d_a = f_a - what_a rho0 from the rest equilibrium (what_a = w_a / I_0):
+ *   LBM_F32  : float d_a
+ *   LBM_F16  : IEEE half of d_a * 2^dev_scale_log2, round to nearest even
+ *   LBM_BF16 : bfloat16 of d_a, round to nearest even                          */
+enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 };
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,        /* bad argument (sizes, tau <= 1/2, null pointer, ...) */
+    LBM_EUNSUPPORTED = -2,  /* valid but not supported (e.g. a non-positive weight) */
+    LBM_EDEVICE = -3,       /* a HIP call failed */
+    LBM_ENONFINITE = -4,    /* a reduction found NaN or Inf */
+    LBM_ESTATE = -5         /* call out of order (e.g. step before init) */
+};
+
+typedef struct {
+    int lattice;        /* LBM_D2V9 or LBM_D3V19 */
+    int stats;          /* LBM_FERMI_DIRAC or LBM_HERMITE */
+    int storage;        /* LBM_F32, LBM_F16 or LBM_BF16 */
+    int nx, ny, nz;     /* grid; nz = 1 for D2V9; each >= 1, nx*ny*nz*Q < 2^31 */
+    double theta, mu;   /* weight parameters (electron model: 1/270 and 1) */
+    double tau;         /* BGK relaxation time in steps, > 1/2 */
+    double E[3];        /* electric acceleration, xi-units per step */
+    double B[3];        /* magnetic field: rotation angle of u per step */
+    double rho0;        /* reference density of the stored deviations (> 0) */
+    int dev_scale_log2; /* LBM_F16 only: stored value is d * 2^dev_scale_log2 (0..24) */
+} lbm_params;
+
+/* Constants the library derives from the parameters (host FP64), exposed for
+ * checking. Shell index k = |e|^2 (0 rest, 1 axis, 2 face diagonal); unused
+ * shells are 0. */
+typedef struct {
+    double I0, I2, I4;            /* weight integrals, eq. (i2n-cont2), Sec. 3 */
+    double c0, c1, c2, c2bar, c2p;/* polynomial coefficients, Sec. 3 (K <= 2) */
+    double J2, Delta2;            /* J_2 = I_2^2/(I_4 I_0), Delta_2, Sec. 3 */
+    double theta_bar;             /* I_2 / I_0, Sec. 9.1 */
+    double cs;                    /* reference speed sqrt(I_2/(3 I_4)), Sec. 8 */
+    double w[4];                  /* quadrature weights by shell, Sec. 8 / Table 1 */
+    double what[4];               /* w / I_0 (sum over the lattice = 1) */
+    double A, Bc;                 /* equilibrium f_a = rho what_a [1 + A (xi.u) */
+    double C[4];                  /*   + Bc (xi.u)^2 + C_k u^2], the reduced EDF of Sec. 9.1 */
+} lbm_constants;
+
+/* Host only, no device work. Computes the constants of Sec. 3, 8 and 9.1 for the
+ * lattice, weight, theta and mu of *p (other fields ignored). Returns LBM_EINVAL for
+ * an unknown lattice/weight or non-finite parameters and LBM_EUNSUPPORTED when a
+ * weight comes out <= 0 (D3V15 under the electron weight). */
+int lbm_compute_constants(const lbm_params *p, lbm_constants *out);
+
+/* Host only. Q, D and the library's lattice vectors e (Q x 3 ints, row a = e_a)
+ * in the order used by every Q-indexed buffer of this library. e may be NULL. */
+int lbm_lattice_info(int lattice, int *Q, int *D, int *e);
+
+/* Host only. Sizes of the device buffers a handle with parameters *p needs:
+ *   state_bytes : one population state (Q arrays of `stride` elements, storage type)
+ *   work_bytes  : scratch for reductions (8-byte aligned)
+ *   adjoint_bytes : one adjoint field (Q x stride floats)
+ *   stride      : elements between population arrays (>= nx*ny*nz)
+ * Any output pointer may be NULL. */
+int lbm_buffer_sizes(const lbm_params *p, size_t *state_bytes, size_t *work_bytes,
+                     size_t *adjoint_bytes, size_t *stride);
+
+/* Validate *p, compute the constants and bind the buffers.
+ *   mask    : device uint8[N], 1 = solid, or NULL (no solids)
+ *   s       : device float[N] in [0, 1], partial bounce-back fraction (Walsh et al.
+ *             2009 gray lattice, not in the paper), or NULL
+ *   state_a, state_b : two device state buffers of state_bytes each (ping-pong)
+ *   work    : device buffer of work_bytes
+ *   stream  : hipStream_t (NULL = default stream)
+ * Errors: LBM_EINVAL (tau <= 1/2, bad sizes, B_x/B_y or E_z in 2D, nz != 1 for D2V9,
+ * null buffer, F16 scale out of range), LBM_EUNSUPPORTED (non-positive weight),
+ * LBM_EDEVICE. On error *out is NULL. */
+int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *state_a,
+               void *state_b, void *work, void *stream, lbm_t *out);
+
+/* Initial state f_a(x) = f^eq_a(rho(x), u(x)) (reduced EDF, Sec. 9.1), no force
+ * correction. rho: device double[N]; u: device double[D*N] SoA (u_x block, then u_y,
+ * ...), xi-units, or NULL for u = 0. Values at solid nodes are ignored. Async. */
+int lbm_init(lbm_t h, const double *rho, const double *u);
+
+/* Advance nsteps >= 0 time steps (collide, force, partial bounce-back, stream,
+ * halfway bounce-back: the discrete BGK update of Sec. 9.1 with the source of Sec. 7).
+ * Async. */
+int lbm_step(lbm_t h, int nsteps);
+
+/* One step from the state in `src` into `dst` (device state buffers of state_bytes,
+ * distinct, neither need be the handle's own); the handle's state is not touched.
+ * Used to recompute trajectories for the adjoint. Async. */
+int lbm_step_from(lbm_t h, const void *src, void *dst);
+
+/* Fields of the current state (pre-collision): rho (device float[N]) and u (device
+ * float[D*N] SoA, xi-units). Solid nodes get 0. Either pointer may be NULL. Async. */
+int lbm_moments(lbm_t h, float *rho, float *u);
+
+/* Totals over fluid nodes of the current state, accumulated in FP64:
+ * out[0] = sum rho, out[1..3] = sum rho u (xi-units; out[3] = 0 in 2D). out is host
+ * memory. Synchronises the stream. LBM_ENONFINITE if any total is NaN/Inf. */
+int lbm_current(lbm_t h, double out[4]);
+
+/* Copy the current state to / from a caller device buffer of state_bytes (the
+ * library's opaque layout: post-collision populations of the previous step). Async. */
+int lbm_get_state(lbm_t h, void *dst);
+int lbm_set_state(lbm_t h, const void *src);
+
+/* Pre-collision populations f_a (full values, not deviations) of a state in FP64:
+ * dst is device double[Q*N], f_a of node n at dst[a*N + n] in lbm_lattice_info order.
+ * state = NULL means the current state. Solid nodes get 0. Async. */
+int lbm_export_f64(lbm_t h, const void *state, double *dst);
+
+/* Change E, B or tau of an existing handle (same validation as lbm_create). */
+int lbm_set_fields(lbm_t h, const double E[3], const double B[3]);
+int lbm_set_tau(lbm_t h, double tau);
+
+/* Adjoint seed for J = (1/norm) sum over fluid nodes x and a of f_a(x, T) xi_a[axis]:
+ * lam[a*stride + n] = xi_a[axis]/norm at fluid nodes, 0 at solids. lam: device float
+ * buffer of adjoint_bytes. Async. */
+int lbm_adjoint_seed(lbm_t h, int axis, double norm, float *lam);
+
+/* One reverse step of the discrete adjoint of lbm_step (not in the paper).
+ *   state   : the state buffer whose populations are pre-collision at step t (what the
+ *             handle held before the forward step t -> t+1)
+ *   lam_in  : dJ/df(t+1) (adjoint_bytes); lam_out: dJ/df(t) (distinct buffer)
+ *   grad_s  : device float[N]; += dJ/ds through this step; may be NULL
+ *   grad_scalars : device double[4]; += (dJ/dE_x, dJ/dE_y, dJ/dE_z, dJ/dtau); may be NULL
+ * Async. */
+int lbm_adjoint_step(lbm_t h, const void *state, const float *lam_in, float *lam_out,
+                     float *grad_s, double *grad_scalars);
+
+void lbm_destroy(lbm_t h);
+const char *lbm_last_error(lbm_t h);
+const char *lbm_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

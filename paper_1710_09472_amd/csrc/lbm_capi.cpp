@@ -1,0 +1,471 @@
+// lbm_capi.cpp -- the extern "C" boundary of the library (declared in include/lbm.h):
+// argument validation, constants, buffer binding and kernel launches on the caller's
+// stream. No device memory is allocated here.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+struct lbm_s {
+    lbm_params p;
+    lbm_constants k;
+    int D = 0, Q = 0;
+    int N = 0, stride = 0;
+    size_t elem = 4;
+    const uint8_t *mask = nullptr;
+    const float *s = nullptr;
+    void *buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    unsigned char *work = nullptr;
+    hipStream_t stream = nullptr;
+    Geometry g{};
+    Physics ph{};
+    bool initialized = false;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int fail(lbm_t h, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(lbm_t h, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (h)
+        h->err = buf;
+    else
+        g_create_error = buf;
+    return code;
+}
+
+int hip_fail(lbm_t h, hipError_t e, const char *what)
+{
+    return fail(h, LBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int lattice_dims(int lattice, int *Q, int *D)
+{
+    if (lattice == LBM_D2V9) {
+        *Q = 9;
+        *D = 2;
+        return LBM_OK;
+    }
+    if (lattice == LBM_D3V19) {
+        *Q = 19;
+        *D = 3;
+        return LBM_OK;
+    }
+    if (lattice == LBM_D3V15) {
+        *Q = 15;
+        *D = 3;
+        return LBM_OK;
+    }
+    return LBM_EINVAL;
+}
+
+size_t elem_size(int storage) { return storage == LBM_F32 ? 4 : 2; }
+
+struct Sizes {
+    int N, stride, nblocks, ntx;
+    size_t state, work, adjoint;
+};
+
+// Validation shared by create and the size query. Writes the message through fail().
+int validate(const lbm_params *p, lbm_t h, Sizes *sz)
+{
+    if (!p) return fail(h, LBM_EINVAL, "null params");
+    int Q, D;
+    if (lattice_dims(p->lattice, &Q, &D) != LBM_OK) return fail(h, LBM_EINVAL, "unknown lattice %d", p->lattice);
+    if (p->stats != LBM_FERMI_DIRAC && p->stats != LBM_HERMITE)
+        return fail(h, LBM_EINVAL, "unknown weight function %d", p->stats);
+    if (p->storage != LBM_F32 && p->storage != LBM_F16 && p->storage != LBM_BF16)
+        return fail(h, LBM_EINVAL, "unknown storage %d", p->storage);
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(h, LBM_EINVAL, "grid sizes must be >= 1");
+    if (D == 2 && p->nz != 1) return fail(h, LBM_EINVAL, "D2V9 needs nz = 1");
+    const double N = (double)p->nx * p->ny * p->nz;
+    const double stride = std::ceil(N / 256.0) * 256.0;
+    if (stride * Q >= 2147483647.0) return fail(h, LBM_EINVAL, "grid too large (Q * N must stay below 2^31)");
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(h, LBM_EINVAL, "tau must be finite and > 1/2");
+    if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return fail(h, LBM_EINVAL, "rho0 must be finite and > 0");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(p->E[i]) || !std::isfinite(p->B[i])) return fail(h, LBM_EINVAL, "E and B must be finite");
+    if (D == 2 && (p->E[2] != 0.0 || p->B[0] != 0.0 || p->B[1] != 0.0))
+        return fail(h, LBM_EINVAL, "2D lattice: only E_x, E_y and B_z may be non-zero");
+    if (p->storage == LBM_F16 && (p->dev_scale_log2 < 0 || p->dev_scale_log2 > 24))
+        return fail(h, LBM_EINVAL, "F16 storage: dev_scale_log2 must be in 0..24");
+    if (p->stats == LBM_FERMI_DIRAC && (!(p->theta > 0) || !std::isfinite(p->theta) || !std::isfinite(p->mu)))
+        return fail(h, LBM_EINVAL, "Fermi-Dirac weight needs finite theta > 0 and finite mu");
+    if (sz) {
+        sz->N = (int)N;
+        sz->stride = (int)stride;
+        sz->ntx = (p->nx + kBlock - 1) / kBlock;
+        sz->nblocks = sz->ntx * p->ny * p->nz;
+        sz->state = (size_t)Q * (size_t)sz->stride * elem_size(p->storage);
+        sz->adjoint = (size_t)Q * (size_t)sz->stride * sizeof(float);
+        const size_t parts = std::max((size_t)kReduceBlocks * 5, (size_t)sz->nblocks * 4);
+        sz->work = 64 + parts * sizeof(double);
+    }
+    return LBM_OK;
+}
+
+void fill_physics(lbm_t h)
+{
+    const lbm_constants &k = h->k;
+    Physics &ph = h->ph;
+    ph = Physics{};
+    ph.rho0 = (float)h->p.rho0;
+    ph.omega = (float)(1.0 / h->p.tau);
+    for (int s = 0; s < 4; ++s) {
+        ph.what[s] = (float)k.what[s];
+        ph.C[s] = (float)k.C[s];
+        ph.Cp[s] = (float)(k.C[s] * k.cs * k.cs);
+    }
+    // lam_k = what_k A / c_s^2. Round the diagonal-shell value to a multiple of 2^-26 and
+    // solve the axis-shell value from n1 lam_1 + n2 lam_2 = 1 (n1, n2: vectors of each
+    // shell with e_x != 0), so the identity holds exactly for the FP32 constants.
+    {
+        const double l2 = k.what[2] * k.A / (k.cs * k.cs);
+        const float l2f = (float)(std::nearbyint(l2 * 67108864.0) / 67108864.0);
+        const double n1 = 2.0, n2 = (h->D == 2) ? 4.0 : 8.0;
+        const float l1f = (float)((1.0 - n2 * (double)l2f) / n1);
+        ph.lam[0] = 0.0f;
+        ph.lam[1] = l1f;
+        ph.lam[2] = l2f;
+        ph.lam[3] = 0.0f;
+    }
+    ph.A = (float)k.A;
+    ph.Bc = (float)k.Bc;
+    ph.cs = (float)k.cs;
+    ph.inv_cs2 = (float)(1.0 / (k.cs * k.cs));
+    for (int i = 0; i < 3; ++i) {
+        ph.E[i] = (float)h->p.E[i];
+        ph.B[i] = (float)h->p.B[i];
+    }
+    if (h->p.storage == LBM_F16) {
+        ph.scale = std::ldexp(1.0f, h->p.dev_scale_log2);
+        ph.inv_scale = std::ldexp(1.0f, -h->p.dev_scale_log2);
+    } else {
+        ph.scale = 1.0f;
+        ph.inv_scale = 1.0f;
+    }
+}
+
+bool has_B(const lbm_t h) { return h->p.B[0] != 0.0 || h->p.B[1] != 0.0 || h->p.B[2] != 0.0; }
+
+double *work_out(lbm_t h) { return reinterpret_cast<double *>(h->work); }
+double *work_parts(lbm_t h) { return reinterpret_cast<double *>(h->work + 64); }
+
+}  // namespace
+
+extern "C" {
+
+const char *lbm_status_string(int status)
+{
+    switch (status) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_EUNSUPPORTED: return "unsupported configuration";
+    case LBM_EDEVICE: return "HIP device error";
+    case LBM_ENONFINITE: return "non-finite value in reduction";
+    case LBM_ESTATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+const char *lbm_last_error(lbm_t h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+int lbm_compute_constants(const lbm_params *p, lbm_constants *out)
+{
+    if (!p || !out) return fail(nullptr, LBM_EINVAL, "null argument");
+    const int rc = compute_constants(p, out);
+    if (rc == LBM_EUNSUPPORTED) return fail(nullptr, rc, "a quadrature weight is not positive for this lattice and weight");
+    if (rc != LBM_OK) return fail(nullptr, rc, "invalid lattice, weight function or weight parameters");
+    return LBM_OK;
+}
+
+int lbm_lattice_info(int lattice, int *Q, int *D, int *e)
+{
+    int q, d;
+    if (lattice_dims(lattice, &q, &d) != LBM_OK || lattice == LBM_D3V15)
+        return fail(nullptr, LBM_EINVAL, "lattice %d has no kernels", lattice);
+    if (Q) *Q = q;
+    if (D) *D = d;
+    if (e) {
+        for (int a = 0; a < q; ++a) {
+            if (lattice == LBM_D2V9) {
+                e[3 * a] = Lat<LBM_D2V9>::ex[a];
+                e[3 * a + 1] = Lat<LBM_D2V9>::ey[a];
+                e[3 * a + 2] = 0;
+            } else {
+                e[3 * a] = Lat<LBM_D3V19>::ex[a];
+                e[3 * a + 1] = Lat<LBM_D3V19>::ey[a];
+                e[3 * a + 2] = Lat<LBM_D3V19>::ez[a];
+            }
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_buffer_sizes(const lbm_params *p, size_t *state_bytes, size_t *work_bytes, size_t *adjoint_bytes,
+                     size_t *stride)
+{
+    Sizes sz;
+    const int rc = validate(p, nullptr, &sz);
+    if (rc != LBM_OK) return rc;
+    if (state_bytes) *state_bytes = sz.state;
+    if (work_bytes) *work_bytes = sz.work;
+    if (adjoint_bytes) *adjoint_bytes = sz.adjoint;
+    if (stride) *stride = (size_t)sz.stride;
+    return LBM_OK;
+}
+
+int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *state_a, void *state_b, void *work,
+               void *stream, lbm_t *out)
+{
+    if (!out) return fail(nullptr, LBM_EINVAL, "null output handle pointer");
+    *out = nullptr;
+    Sizes sz;
+    int rc = validate(p, nullptr, &sz);
+    if (rc != LBM_OK) return rc;
+    if (p->lattice == LBM_D3V15) {
+        lbm_constants k;
+        rc = compute_constants(p, &k);
+        return fail(nullptr, rc == LBM_OK ? LBM_EUNSUPPORTED : rc,
+                    "D3V15 is not supported (its rest weight is negative under the electron weight)");
+    }
+    if (!state_a || !state_b || !work) return fail(nullptr, LBM_EINVAL, "state_a, state_b and work are required");
+    if (state_a == state_b) return fail(nullptr, LBM_EINVAL, "state_a and state_b must be distinct buffers");
+    lbm_s *h = new (std::nothrow) lbm_s;
+    if (!h) return fail(nullptr, LBM_EDEVICE, "out of host memory");
+    h->p = *p;
+    rc = compute_constants(p, &h->k);
+    if (rc != LBM_OK) {
+        delete h;
+        return fail(nullptr, rc, rc == LBM_EUNSUPPORTED ? "a quadrature weight is not positive"
+                                                          : "invalid weight parameters");
+    }
+    lattice_dims(p->lattice, &h->Q, &h->D);
+    h->N = sz.N;
+    h->stride = sz.stride;
+    h->elem = elem_size(p->storage);
+    h->mask = mask;
+    h->s = s;
+    h->buf[0] = state_a;
+    h->buf[1] = state_b;
+    h->work = static_cast<unsigned char *>(work);
+    h->stream = static_cast<hipStream_t>(stream);
+    h->g.nx = p->nx;
+    h->g.ny = p->ny;
+    h->g.nz = p->nz;
+    h->g.stride = sz.stride;
+    h->g.ntx = sz.ntx;
+    h->g.nblocks = sz.nblocks;
+    h->g.mask = mask;
+    h->g.s = s;
+    fill_physics(h);
+    *out = h;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_t h) { delete h; }
+
+int lbm_init(lbm_t h, const double *rho, const double *u)
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    if (!rho) return fail(h, LBM_EINVAL, "rho is required");
+    InitArgs a{};
+    a.g = h->g;
+    a.ph = h->ph;
+    a.rho = rho;
+    a.u = u;
+    a.dst = h->buf[h->cur];
+    const hipError_t e = launch_init(h->p.lattice, h->p.storage, a, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "init kernel launch");
+    h->initialized = true;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_t h, int nsteps)
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    if (nsteps < 0) return fail(h, LBM_EINVAL, "nsteps must be >= 0");
+    if (!h->initialized) return fail(h, LBM_ESTATE, "lbm_step before lbm_init or lbm_set_state");
+    StepArgs a{};
+    a.g = h->g;
+    a.ph = h->ph;
+    const bool mag = has_B(h);
+    for (int t = 0; t < nsteps; ++t) {
+        a.src = h->buf[h->cur];
+        a.dst = h->buf[h->cur ^ 1];
+        const hipError_t e = launch_step(h->p.lattice, h->p.storage, mag, a, h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "step kernel launch");
+        h->cur ^= 1;
+    }
+    return LBM_OK;
+}
+
+int lbm_step_from(lbm_t h, const void *src, void *dst)
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    if (!src || !dst || src == dst) return fail(h, LBM_EINVAL, "src and dst must be distinct non-null buffers");
+    StepArgs a{};
+    a.g = h->g;
+    a.ph = h->ph;
+    a.src = src;
+    a.dst = dst;
+    const hipError_t e = launch_step(h->p.lattice, h->p.storage, has_B(h), a, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "step kernel launch");
+    return LBM_OK;
+}
+
+static int gather_common(lbm_t h, const void *state, float *rho, float *u, double *f64, double *parts)
+{
+    GatherArgs a{};
+    a.g = h->g;
+    a.ph = h->ph;
+    a.src = state ? state : h->buf[h->cur];
+    a.rho = rho;
+    a.u = u;
+    a.f64 = f64;
+    a.partials = parts;
+    a.N = h->N;
+    for (int k = 0; k < 4; ++k) a.what_rho0[k] = h->k.what[k] * h->p.rho0;
+    const hipError_t e = launch_gather(h->p.lattice, h->p.storage, a, kReduceBlocks, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "gather kernel launch");
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_t h, float *rho, float *u)
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    if (!h->initialized) return fail(h, LBM_ESTATE, "lbm_moments before lbm_init or lbm_set_state");
+    if (!rho && !u) return LBM_OK;
+    return gather_common(h, nullptr, rho, u, nullptr, nullptr);
+}
+
+int lbm_export_f64(lbm_t h, const void *state, double *dst)
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    if (!dst) return fail(h, LBM_EINVAL, "dst is required");
+    if (!state && !h->initialized) return fail(h, LBM_ESTATE, "export of the current state before init");
+    return gather_common(h, state, nullptr, nullptr, dst, nullptr);
+}
+
+int lbm_current(lbm_t h, double out[4])
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    if (!out) return fail(h, LBM_EINVAL, "out is required");
+    if (!h->initialized) return fail(h, LBM_ESTATE, "lbm_current before lbm_init or lbm_set_state");
+    int rc = gather_common(h, nullptr, nullptr, nullptr, nullptr, work_parts(h));
+    if (rc != LBM_OK) return rc;
+    hipError_t e = launch_reduce_final(work_parts(h), kReduceBlocks, 5, work_out(h), 0, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "reduce kernel launch");
+    double tot[5];
+    e = hipMemcpyAsync(tot, work_out(h), sizeof(tot), hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "copy of totals");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "stream synchronize");
+    // tot = (sum drho, sum d e_x, sum d e_y, sum d e_z, fluid nodes); momentum to xi-units
+    out[0] = tot[4] * h->p.rho0 + tot[0];
+    for (int i = 0; i < 3; ++i) out[1 + i] = tot[1 + i] / h->k.cs;
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(out[i])) return fail(h, LBM_ENONFINITE, "non-finite total (component %d)", i);
+    return LBM_OK;
+}
+
+int lbm_get_state(lbm_t h, void *dst)
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    if (!dst) return fail(h, LBM_EINVAL, "dst is required");
+    const hipError_t e = hipMemcpyAsync(dst, h->buf[h->cur], (size_t)h->Q * h->stride * h->elem,
+                                        hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "state copy");
+    return LBM_OK;
+}
+
+int lbm_set_state(lbm_t h, const void *src)
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    if (!src) return fail(h, LBM_EINVAL, "src is required");
+    const hipError_t e = hipMemcpyAsync(h->buf[h->cur], src, (size_t)h->Q * h->stride * h->elem,
+                                        hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "state copy");
+    h->initialized = true;
+    return LBM_OK;
+}
+
+int lbm_set_fields(lbm_t h, const double E[3], const double B[3])
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    if (!E || !B) return fail(h, LBM_EINVAL, "E and B are required");
+    lbm_params q = h->p;
+    for (int i = 0; i < 3; ++i) {
+        q.E[i] = E[i];
+        q.B[i] = B[i];
+    }
+    const int rc = validate(&q, h, nullptr);
+    if (rc != LBM_OK) return rc;
+    h->p = q;
+    fill_physics(h);
+    return LBM_OK;
+}
+
+int lbm_set_tau(lbm_t h, double tau)
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    lbm_params q = h->p;
+    q.tau = tau;
+    const int rc = validate(&q, h, nullptr);
+    if (rc != LBM_OK) return rc;
+    h->p = q;
+    fill_physics(h);
+    return LBM_OK;
+}
+
+int lbm_adjoint_seed(lbm_t h, int axis, double norm, float *lam)
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    if (!lam) return fail(h, LBM_EINVAL, "lam is required");
+    if (axis < 0 || axis >= h->D) return fail(h, LBM_EINVAL, "axis must be in 0..D-1");
+    if (!(norm != 0.0) || !std::isfinite(norm)) return fail(h, LBM_EINVAL, "norm must be finite and non-zero");
+    const hipError_t e = launch_seed(h->p.lattice, h->g, (float)(1.0 / (h->k.cs * norm)), axis, lam, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "seed kernel launch");
+    return LBM_OK;
+}
+
+int lbm_adjoint_step(lbm_t h, const void *state, const float *lam_in, float *lam_out, float *grad_s,
+                     double *grad_scalars)
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    if (!state || !lam_in || !lam_out) return fail(h, LBM_EINVAL, "state, lam_in and lam_out are required");
+    if (lam_in == lam_out) return fail(h, LBM_EINVAL, "lam_in and lam_out must be distinct buffers");
+    AdjointArgs a{};
+    a.g = h->g;
+    a.ph = h->ph;
+    a.state = state;
+    a.lam_in = lam_in;
+    a.lam_out = lam_out;
+    a.grad_s = grad_s;
+    a.partials = work_parts(h);
+    hipError_t e = launch_adjoint(h->p.lattice, h->p.storage, has_B(h), a, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "adjoint kernel launch");
+    if (grad_scalars) {
+        e = launch_reduce_final(work_parts(h), h->g.nblocks, 4, grad_scalars, 1, h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "reduce kernel launch");
+    }
+    return LBM_OK;
+}
+
+}  // extern "C"

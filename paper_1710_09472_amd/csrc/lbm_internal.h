@@ -1,0 +1,122 @@
+// lbm_internal.h -- shared definitions of the library: lattice tables, kernel argument
+// blocks and the kernel launchers. Not part of the public ABI (see include/lbm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lbm.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------------
+// Lattice vectors e_a (Sec. 8, Table 1) in the library's order, with opposites.
+// D2V9: rest, 4 axis, 4 diagonals. D3V19: rest, 6 axis, 12 face diagonals; every
+// non-rest vector at an odd index is followed by its opposite.
+// ---------------------------------------------------------------------------------
+template <int LAT>
+struct Lat;
+
+template <>
+struct Lat<LBM_D2V9> {
+    static constexpr int Q = 9, D = 2;
+    static constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static constexpr int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    static constexpr int ez[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+};
+
+template <>
+struct Lat<LBM_D3V19> {
+    static constexpr int Q = 19, D = 3;
+    static constexpr int ex[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static constexpr int ey[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static constexpr int ez[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static constexpr int opp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+};
+
+// ---------------------------------------------------------------------------------
+// Kernel argument block (passed by value). Float constants are the FP64 host constants
+// rounded once to FP32.
+// ---------------------------------------------------------------------------------
+struct Geometry {
+    int nx, ny, nz;
+    int stride;       // elements between population arrays
+    int ntx;          // 256-node tiles per x row
+    int nblocks;      // tiles in the grid = ntx * ny * nz
+    const uint8_t *mask;  // nullable
+    const float *s;       // nullable
+};
+
+struct Physics {
+    float rho0;
+    float omega;      // 1 / tau
+    float what[4];    // w_k / I_0 by shell k = |e|^2
+    float lam[4];     // what_k A / c_s^2: weight of e.j in the equilibrium, rounded so that
+                      // sum_a lam_a e_a e_a = identity holds exactly in FP32 constants
+    float A, Bc;      // reduced EDF coefficients
+    float C[4];       // C_k (source term)
+    float Cp[4];      // C_k c_s^2 (equilibrium, U = u / c_s)
+    float cs, inv_cs2;
+    float E[3];       // xi-units per step
+    float B[3];
+    float scale, inv_scale;  // storage scale (F16: 2^k), 1 otherwise
+};
+
+struct StepArgs {
+    Geometry g;
+    Physics ph;
+    const void *src;
+    void *dst;
+};
+
+struct InitArgs {
+    Geometry g;
+    Physics ph;
+    const double *rho;
+    const double *u;  // nullable
+    void *dst;
+};
+
+struct GatherArgs {
+    Geometry g;
+    Physics ph;
+    const void *src;
+    float *rho;       // nullable
+    float *u;         // nullable
+    double *f64;      // nullable (export)
+    double *partials; // nullable (reduction)
+    double what_rho0[4];  // what_k rho0 in FP64 (export of full populations)
+    int N;
+};
+
+struct AdjointArgs {
+    Geometry g;
+    Physics ph;
+    const void *state;
+    const float *lam_in;
+    float *lam_out;
+    float *grad_s;    // nullable
+    double *partials; // per-block (dE_x, dE_y, dE_z, dtau)
+};
+
+// Launchers (lbm_kernels.hip). Each returns hipSuccess or the launch error.
+hipError_t launch_step(int lattice, int storage, bool mag, const StepArgs &a, hipStream_t st);
+hipError_t launch_init(int lattice, int storage, const InitArgs &a, hipStream_t st);
+hipError_t launch_gather(int lattice, int storage, const GatherArgs &a, int nblocks_reduce,
+                         hipStream_t st);
+hipError_t launch_reduce_final(const double *partials, int nparts, int ncomp, double *out,
+                               int accumulate, hipStream_t st);
+hipError_t launch_adjoint(int lattice, int storage, bool mag, const AdjointArgs &a, hipStream_t st);
+hipError_t launch_seed(int lattice, const Geometry &g, float value_per_unit_e, int axis, float *lam,
+                       hipStream_t st);
+
+// Host constants (lbm_consts.cpp).
+int weight_integrals(int stats, int D, double theta, double mu, double out[4]);
+int compute_constants(const lbm_params *p, lbm_constants *k);
+
+constexpr int kBlock = 256;        // threads per block of the node kernels
+constexpr int kReduceBlocks = 1024;  // blocks of the gather/reduce kernel
+
+}  // namespace lbm

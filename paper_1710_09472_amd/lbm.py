@@ -1,0 +1,288 @@
+"""ctypes binding of the HIP library ``liblbm_hip.so`` (C ABI in ``include/lbm.h``).
+
+This module only marshals arguments: every step of the lattice Boltzmann update runs in
+the library's kernels. PyTorch provides device memory and the HIP stream. If the
+library has not been built, loading fails with an error; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import numpy as np
+
+PKG = Path(__file__).resolve().parent
+LIB_PATH = PKG / "liblbm_hip.so"
+
+LATTICES = {"D2V9": 0, "D3V19": 1, "D3V15": 2}
+STATS = {"fd": 0, "hermite": 2}
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+
+LBM_OK, LBM_EINVAL, LBM_EUNSUPPORTED, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+
+#: Every function the header declares (checked by the tests).
+EXPORTS = [
+    "lbm_compute_constants", "lbm_lattice_info", "lbm_buffer_sizes", "lbm_create", "lbm_init",
+    "lbm_step", "lbm_step_from", "lbm_moments", "lbm_current", "lbm_get_state", "lbm_set_state",
+    "lbm_export_f64", "lbm_set_fields", "lbm_set_tau", "lbm_adjoint_seed", "lbm_adjoint_step",
+    "lbm_destroy", "lbm_last_error", "lbm_status_string",
+]
+
+
+class LbmParams(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int), ("stats", ctypes.c_int), ("storage", ctypes.c_int),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("theta", ctypes.c_double), ("mu", ctypes.c_double), ("tau", ctypes.c_double),
+        ("E", ctypes.c_double * 3), ("B", ctypes.c_double * 3), ("rho0", ctypes.c_double),
+        ("dev_scale_log2", ctypes.c_int),
+    ]
+
+
+class LbmConstants(ctypes.Structure):
+    _fields_ = [
+        ("I0", ctypes.c_double), ("I2", ctypes.c_double), ("I4", ctypes.c_double),
+        ("c0", ctypes.c_double), ("c1", ctypes.c_double), ("c2", ctypes.c_double),
+        ("c2bar", ctypes.c_double), ("c2p", ctypes.c_double),
+        ("J2", ctypes.c_double), ("Delta2", ctypes.c_double), ("theta_bar", ctypes.c_double),
+        ("cs", ctypes.c_double), ("w", ctypes.c_double * 4), ("what", ctypes.c_double * 4),
+        ("A", ctypes.c_double), ("Bc", ctypes.c_double), ("C", ctypes.c_double * 4),
+    ]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} [status {code}]")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load the built library (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1710_09472_amd.build`")
+        lib = ctypes.CDLL(str(LIB_PATH))
+        vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        sz = ctypes.POINTER(ctypes.c_size_t)
+        P = ctypes.POINTER(LbmParams)
+        lib.lbm_compute_constants.argtypes = [P, ctypes.POINTER(LbmConstants)]
+        lib.lbm_lattice_info.argtypes = [i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
+        lib.lbm_buffer_sizes.argtypes = [P, sz, sz, sz, sz]
+        lib.lbm_create.argtypes = [P, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
+        lib.lbm_init.argtypes = [vp, vp, vp]
+        lib.lbm_step.argtypes = [vp, i]
+        lib.lbm_step_from.argtypes = [vp, vp, vp]
+        lib.lbm_moments.argtypes = [vp, vp, vp]
+        lib.lbm_current.argtypes = [vp, ctypes.POINTER(d)]
+        lib.lbm_get_state.argtypes = [vp, vp]
+        lib.lbm_set_state.argtypes = [vp, vp]
+        lib.lbm_export_f64.argtypes = [vp, vp, vp]
+        lib.lbm_set_fields.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(d)]
+        lib.lbm_set_tau.argtypes = [vp, d]
+        lib.lbm_adjoint_seed.argtypes = [vp, i, d, vp]
+        lib.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp]
+        lib.lbm_destroy.argtypes = [vp]
+        lib.lbm_destroy.restype = None
+        lib.lbm_last_error.argtypes = [vp]
+        lib.lbm_last_error.restype = ctypes.c_char_p
+        lib.lbm_status_string.argtypes = [i]
+        lib.lbm_status_string.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("lbm_destroy", "lbm_last_error", "lbm_status_string"):
+                getattr(lib, name).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _check(rc, handle=None):
+    if rc != LBM_OK:
+        lib = load_library()
+        msg = lib.lbm_last_error(handle).decode()
+        raise LbmError(rc, msg or lib.lbm_status_string(rc).decode())
+
+
+def make_params(lattice="D2V9", nx=1, ny=1, nz=1, tau=0.8, E=(0.0, 0.0, 0.0), B=(0.0, 0.0, 0.0),
+                storage="f32", dev_scale_log2=0, rho0=1.0, stats="fd", theta=1.0 / 270.0, mu=1.0) -> LbmParams:
+    p = LbmParams()
+    p.lattice = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
+    p.stats = STATS[stats] if isinstance(stats, str) else int(stats)
+    p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    p.theta, p.mu, p.tau = float(theta), float(mu), float(tau)
+    p.E = (ctypes.c_double * 3)(*[float(v) for v in E])
+    p.B = (ctypes.c_double * 3)(*[float(v) for v in B])
+    p.rho0 = float(rho0)
+    p.dev_scale_log2 = int(dev_scale_log2)
+    return p
+
+
+def compute_constants(lattice="D2V9", stats="fd", theta=1.0 / 270.0, mu=1.0) -> dict:
+    """Host-side constants of the library (no GPU needed)."""
+    lib = load_library()
+    out = LbmConstants()
+    _check(lib.lbm_compute_constants(ctypes.byref(make_params(lattice, stats=stats, theta=theta, mu=mu)),
+                                     ctypes.byref(out)))
+    res = {}
+    for name, typ in LbmConstants._fields_:
+        v = getattr(out, name)
+        res[name] = list(v) if hasattr(v, "__len__") else float(v)
+    return res
+
+
+def lattice_info(lattice="D2V9"):
+    """(Q, D, e) with e an int array (Q, 3) in the library's velocity order."""
+    lib = load_library()
+    Q, D = ctypes.c_int(), ctypes.c_int()
+    e = (ctypes.c_int * (27 * 3))()
+    _check(lib.lbm_lattice_info(LATTICES[lattice], ctypes.byref(Q), ctypes.byref(D), e))
+    return Q.value, D.value, np.array(e[: 3 * Q.value], dtype=np.int64).reshape(Q.value, 3)
+
+
+def buffer_sizes(params: LbmParams) -> dict:
+    lib = load_library()
+    st, wk, ad, sd = (ctypes.c_size_t() for _ in range(4))
+    _check(lib.lbm_buffer_sizes(ctypes.byref(params), ctypes.byref(st), ctypes.byref(wk), ctypes.byref(ad),
+                                ctypes.byref(sd)))
+    return {"state": st.value, "work": wk.value, "adjoint": ad.value, "stride": sd.value}
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Simulation:
+    """One lattice Boltzmann handle with its device buffers (torch tensors).
+
+    Geometry arrays: ``mask`` (uint8, 1 = solid) and ``s`` (partial bounce-back
+    fraction in [0, 1]) of N nodes, numpy or torch; they are copied to the device once.
+    """
+
+    def __init__(self, lattice="D2V9", nx=1, ny=1, nz=1, tau=0.8, E=(0.0, 0.0, 0.0), B=(0.0, 0.0, 0.0),
+                 storage="f32", dev_scale_log2=0, rho0=1.0, stats="fd", theta=1.0 / 270.0, mu=1.0,
+                 mask=None, s=None, device="cuda"):
+        import torch
+
+        self.torch = torch
+        self.lib = load_library()
+        self.lattice = lattice
+        self.params = make_params(lattice, nx, ny, nz, tau, E, B, storage, dev_scale_log2, rho0, stats, theta, mu)
+        self.sizes = buffer_sizes(self.params)
+        self.Q, self.D, self.e = lattice_info(lattice)
+        self.N = nx * ny * nz
+        self.stride = self.sizes["stride"]
+        self.device = torch.device(device)
+        self.mask = None if mask is None else self._field(mask, torch.uint8)
+        self.s = None if s is None else self._field(s, torch.float32)
+        for name, arr in (("mask", self.mask), ("s", self.s)):
+            if arr is not None and arr.numel() != self.N:
+                raise ValueError(f"{name} must have {self.N} entries")
+        self.bufs = [torch.zeros(self.sizes["state"], dtype=torch.uint8, device=self.device) for _ in range(2)]
+        self.work = torch.zeros(self.sizes["work"], dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(self.lib.lbm_create(ctypes.byref(self.params), _ptr(self.mask), _ptr(self.s), _ptr(self.bufs[0]),
+                                   _ptr(self.bufs[1]), _ptr(self.work), ctypes.c_void_p(self.stream.cuda_stream),
+                                   ctypes.byref(h)))
+        self.h = h
+        self.constants = compute_constants(lattice, stats, theta, mu)
+
+    def _field(self, a, dtype):
+        torch = self.torch
+        if isinstance(a, torch.Tensor):
+            t = a.detach()
+        else:
+            t = torch.as_tensor(np.asarray(a))
+        return t.to(device=self.device, dtype=dtype).reshape(-1).contiguous()
+
+    # ------------------------------------------------------------------ lifecycle
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a, dtype):
+        t = self.torch.as_tensor(a) if not isinstance(a, self.torch.Tensor) else a
+        return t.to(device=self.device, dtype=dtype).contiguous()
+
+    # ------------------------------------------------------------------ forward
+    def init(self, rho, u=None):
+        """f = f^eq(rho, u); rho (N,), u (D, N) or None, xi-units."""
+        self._rho_in = self._dev(rho, self.torch.float64).reshape(-1)
+        self._u_in = None if u is None else self._dev(u, self.torch.float64).reshape(-1)
+        if self._rho_in.numel() != self.N or (self._u_in is not None and self._u_in.numel() != self.D * self.N):
+            raise ValueError("rho must have N entries and u D*N")
+        _check(self.lib.lbm_init(self.h, _ptr(self._rho_in), _ptr(self._u_in)), self.h)
+
+    def step(self, n=1):
+        _check(self.lib.lbm_step(self.h, int(n)), self.h)
+
+    def step_from(self, src, dst):
+        _check(self.lib.lbm_step_from(self.h, _ptr(src), _ptr(dst)), self.h)
+
+    def moments(self):
+        """(rho (N,), u (D, N)) float32 device tensors of the current state."""
+        rho = self.torch.empty(self.N, dtype=self.torch.float32, device=self.device)
+        u = self.torch.empty(self.D * self.N, dtype=self.torch.float32, device=self.device)
+        _check(self.lib.lbm_moments(self.h, _ptr(rho), _ptr(u)), self.h)
+        return rho, u.reshape(self.D, self.N)
+
+    def current(self):
+        """(sum rho, sum rho u_x, sum rho u_y, sum rho u_z) over fluid nodes, FP64."""
+        out = (ctypes.c_double * 4)()
+        _check(self.lib.lbm_current(self.h, out), self.h)
+        return np.array(out[:])
+
+    def export_f64(self, state=None):
+        """Pre-collision populations (Q, N) float64 in library order."""
+        out = self.torch.empty(self.Q * self.N, dtype=self.torch.float64, device=self.device)
+        _check(self.lib.lbm_export_f64(self.h, _ptr(state), _ptr(out)), self.h)
+        return out.reshape(self.Q, self.N)
+
+    def new_state(self):
+        return self.torch.zeros(self.sizes["state"], dtype=self.torch.uint8, device=self.device)
+
+    def get_state(self, dst=None):
+        dst = self.new_state() if dst is None else dst
+        _check(self.lib.lbm_get_state(self.h, _ptr(dst)), self.h)
+        return dst
+
+    def set_state(self, src):
+        _check(self.lib.lbm_set_state(self.h, _ptr(src)), self.h)
+
+    def set_fields(self, E, B=(0.0, 0.0, 0.0)):
+        e = (ctypes.c_double * 3)(*[float(v) for v in E])
+        b = (ctypes.c_double * 3)(*[float(v) for v in B])
+        _check(self.lib.lbm_set_fields(self.h, e, b), self.h)
+        self.params.E, self.params.B = e, b
+
+    def set_tau(self, tau):
+        _check(self.lib.lbm_set_tau(self.h, float(tau)), self.h)
+        self.params.tau = float(tau)
+
+    # ------------------------------------------------------------------ adjoint
+    def new_adjoint(self):
+        return self.torch.zeros(self.sizes["adjoint"] // 4, dtype=self.torch.float32, device=self.device)
+
+    def adjoint_seed(self, axis=0, norm=None, lam=None):
+        lam = self.new_adjoint() if lam is None else lam
+        _check(self.lib.lbm_adjoint_seed(self.h, int(axis), float(self.N if norm is None else norm), _ptr(lam)),
+               self.h)
+        return lam
+
+    def adjoint_step(self, state, lam_in, lam_out, grad_s=None, grad_scalars=None):
+        _check(self.lib.lbm_adjoint_step(self.h, _ptr(state), _ptr(lam_in), _ptr(lam_out), _ptr(grad_s),
+                                         _ptr(grad_scalars)), self.h)
+
+    def adjoint_view(self, lam):
+        """(Q, N) view of an adjoint buffer (drops the stride padding)."""
+        return lam.reshape(self.Q, self.stride)[:, : self.N]

@@ -1,0 +1,137 @@
+"""The C-ABI library on the host (no GPU): it loads, exports every symbol the header
+declares, validates parameters, and its FP64 constants agree with the oracle's
+independent mpmath computation and with the values the paper prints."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1710_09472_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def _header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    lib = lbm.load_library()
+    names = _header_functions()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(lbm.EXPORTS) == names
+
+
+@pytest.mark.parametrize("lattice,D", [("D2V9", 2), ("D3V19", 3)])
+def test_constants_match_oracle(lattice, D):
+    from oracle import constants as K
+
+    c = lbm.compute_constants(lattice)
+    k = K.coefficients(D)
+    lw = K.lattice_weights(lattice)
+    pairs = {"I0": k.I0, "I2": k.I2, "I4": k.I4, "c0": k.c0, "c1": k.c1, "c2": k.c2, "c2bar": k.c2bar,
+             "c2p": k.c2p, "J2": k.J2, "Delta2": k.Delta2, "theta_bar": k.thetabar, "cs": k.cs}
+    for name, ref in pairs.items():
+        assert abs(c[name] / float(ref) - 1) < 1e-14, name
+    for sh in (0, 1, 2):
+        assert abs(c["w"][sh] / float(lw["w"][sh]) - 1) < 1e-14
+        assert abs(c["what"][sh] / float(lw["w"][sh] / k.I0) - 1) < 1e-14
+
+
+@pytest.mark.parametrize("lattice,fname", [("D2V9", "paper_constants_2d.txt"), ("D3V19", "paper_constants_3d.txt")])
+def test_constants_match_printed_tables(lattice, fname):
+    """The library's FP64 constants against the printed 24-digit tables of Sec. 9.1."""
+    gold = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", fname)):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            gold[k] = float(v)
+    c = lbm.compute_constants(lattice)
+    ours = {"c0": c["c0"], "c1": c["c1"], "c2": c["c2"], "c2bar": c["c2bar"], "c2p": c["c2p"],
+            "thetabar": c["theta_bar"], "w0": c["w"][0], "ws": c["w"][1], "wl": c["w"][2], "cs": c["cs"]}
+    for k, v in gold.items():
+        assert abs(ours[k] / v - 1) < 1e-14, (k, ours[k], v)
+
+
+@pytest.mark.parametrize("lattice", ["D2V9", "D3V19"])
+def test_collapsed_equilibrium_matches_oracle(lattice):
+    """what_a [1 + A xi.u + Bc (xi.u)^2 + C_k u^2] rho equals the oracle's reduced EDF."""
+    from oracle.oracle import OracleModel
+
+    c = lbm.compute_constants(lattice)
+    m = OracleModel(lattice, 2, 2, 1 if lattice == "D2V9" else 2)
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        rho, u = rng.uniform(0.5, 2), rng.uniform(-0.05, 0.05, m.D)
+        xu = m.xi[:, : m.D] @ u
+        sh = (m.e ** 2).sum(1)
+        lib_feq = rho * np.array(c["what"])[sh] * (1 + c["A"] * xu + c["Bc"] * xu ** 2 + np.array(c["C"])[sh] * (u @ u))
+        np.testing.assert_allclose(lib_feq, m.equilibrium(rho, u), rtol=1e-13)
+
+
+def test_hermite_constants():
+    for lat, w in (("D2V9", [4 / 9, 1 / 9, 1 / 36]), ("D3V19", [1 / 3, 1 / 18, 1 / 36])):
+        c = lbm.compute_constants(lat, stats="hermite")
+        np.testing.assert_allclose(c["w"][:3], w, rtol=1e-15)
+        assert abs(c["cs"] - 1 / np.sqrt(3)) < 1e-15
+
+
+def test_lattice_vectors_and_opposites():
+    from oracle import constants as K
+
+    for lat in ("D2V9", "D3V19"):
+        Q, D, e = lbm.lattice_info(lat)
+        ours = sorted(tuple(v[:D]) for v in e)
+        assert ours == sorted(K.lattice_vectors(lat))
+        assert len(set(ours)) == Q
+
+
+def _rc(params):
+    try:
+        lbm.buffer_sizes(params)
+        return 0
+    except lbm.LbmError as err:
+        return err.code
+
+
+def test_parameter_validation():
+    ok = lbm.make_params("D2V9", 64, 32)
+    assert _rc(ok) == 0
+    assert _rc(lbm.make_params("D2V9", 64, 32, tau=0.5)) == lbm.LBM_EINVAL
+    assert _rc(lbm.make_params("D2V9", 64, 32, tau=float("nan"))) == lbm.LBM_EINVAL
+    assert _rc(lbm.make_params("D2V9", 64, 32, nz=2)) == lbm.LBM_EINVAL
+    assert _rc(lbm.make_params("D2V9", 64, 32, B=(1e-3, 0, 0))) == lbm.LBM_EINVAL
+    assert _rc(lbm.make_params("D2V9", 64, 32, E=(0, 0, 1e-3))) == lbm.LBM_EINVAL
+    assert _rc(lbm.make_params("D2V9", 0, 32)) == lbm.LBM_EINVAL
+    assert _rc(lbm.make_params("D3V19", 1024, 1024, 1024)) == lbm.LBM_EINVAL  # Q*N >= 2^31
+    assert _rc(lbm.make_params("D2V9", 8, 8, storage="f16", dev_scale_log2=30)) == lbm.LBM_EINVAL
+    assert _rc(lbm.make_params("D2V9", 8, 8, rho0=0.0)) == lbm.LBM_EINVAL
+    assert _rc(lbm.make_params(7, 8, 8)) == lbm.LBM_EINVAL
+
+
+def test_create_rejections_without_device_work():
+    lib = lbm.load_library()
+    h = ctypes.c_void_p()
+    p = lbm.make_params("D2V9", 8, 8)
+    rc = lib.lbm_create(ctypes.byref(p), None, None, None, None, None, None, ctypes.byref(h))
+    assert rc == lbm.LBM_EINVAL and not h.value
+    p15 = lbm.make_params("D3V15", 8, 8, 8)
+    dummy = ctypes.c_void_p(4096)
+    rc = lib.lbm_create(ctypes.byref(p15), None, None, dummy, ctypes.c_void_p(8192), dummy, None, ctypes.byref(h))
+    assert rc == lbm.LBM_EUNSUPPORTED and not h.value
+    assert b"D3V15" in lib.lbm_last_error(None)
+    assert lib.lbm_status_string(lbm.LBM_ENONFINITE) == b"non-finite value in reduction"
+
+
+def test_buffer_sizes():
+    s = lbm.buffer_sizes(lbm.make_params("D2V9", 4096, 4096))
+    assert s["stride"] == 4096 * 4096 and s["state"] == 9 * 4096 * 4096 * 4
+    s16 = lbm.buffer_sizes(lbm.make_params("D2V9", 300, 7, storage="bf16"))
+    assert s16["stride"] == 2304 and s16["state"] == 9 * 2304 * 2 and s16["adjoint"] == 9 * 2304 * 4
