@@ -71,7 +71,7 @@ typedef struct {
     double E[3];        /* electric acceleration, xi-units per step */
     double B[3];        /* magnetic field: rotation angle of u per step */
     double rho0;        /* reference density of the stored deviations (> 0) */
-    int dev_scale_log2; /* LBM_F16 only: stored value is d * 2^dev_scale_log2 (0..24) */
+    int dev_scale_log2; /* LBM_F16 only: stored value is d * 2^dev_scale_log2 (0..40) */
 } lbm_params;
 
 /* Constants the library derives from the parameters (host FP64), exposed for

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -12,6 +13,19 @@
 #include "lbm_internal.h"
 
 using namespace lbm;
+
+// Extra elements between population arrays (a multiple of 256), so that the Q arrays do
+// not all start at the same offset modulo large powers of two (measured: +1-4 % on
+// MI355X). LBM_STRIDE_PAD overrides it (rounded to a multiple of 256).
+static int stride_pad()
+{
+    static const int pad = [] {
+        const char *e = std::getenv("LBM_STRIDE_PAD");
+        const int v = e ? std::atoi(e) : 1024;
+        return v < 0 ? 0 : (v + 255) / 256 * 256;
+    }();
+    return pad;
+}
 
 struct lbm_s {
     lbm_params p;
@@ -27,6 +41,7 @@ struct lbm_s {
     hipStream_t stream = nullptr;
     Geometry g{};
     Physics ph{};
+    void *links = nullptr;  // per-node link masks inside the work buffer
     bool initialized = false;
     std::string err;
 };
@@ -95,7 +110,7 @@ int validate(const lbm_params *p, lbm_t h, Sizes *sz)
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(h, LBM_EINVAL, "grid sizes must be >= 1");
     if (D == 2 && p->nz != 1) return fail(h, LBM_EINVAL, "D2V9 needs nz = 1");
     const double N = (double)p->nx * p->ny * p->nz;
-    const double stride = std::ceil(N / 256.0) * 256.0;
+    const double stride = std::ceil(N / 256.0) * 256.0 + stride_pad();
     if (stride * Q >= 2147483647.0) return fail(h, LBM_EINVAL, "grid too large (Q * N must stay below 2^31)");
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(h, LBM_EINVAL, "tau must be finite and > 1/2");
     if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return fail(h, LBM_EINVAL, "rho0 must be finite and > 0");
@@ -103,8 +118,8 @@ int validate(const lbm_params *p, lbm_t h, Sizes *sz)
         if (!std::isfinite(p->E[i]) || !std::isfinite(p->B[i])) return fail(h, LBM_EINVAL, "E and B must be finite");
     if (D == 2 && (p->E[2] != 0.0 || p->B[0] != 0.0 || p->B[1] != 0.0))
         return fail(h, LBM_EINVAL, "2D lattice: only E_x, E_y and B_z may be non-zero");
-    if (p->storage == LBM_F16 && (p->dev_scale_log2 < 0 || p->dev_scale_log2 > 24))
-        return fail(h, LBM_EINVAL, "F16 storage: dev_scale_log2 must be in 0..24");
+    if (p->storage == LBM_F16 && (p->dev_scale_log2 < 0 || p->dev_scale_log2 > 40))
+        return fail(h, LBM_EINVAL, "F16 storage: dev_scale_log2 must be in 0..40");
     if (p->stats == LBM_FERMI_DIRAC && (!(p->theta > 0) || !std::isfinite(p->theta) || !std::isfinite(p->mu)))
         return fail(h, LBM_EINVAL, "Fermi-Dirac weight needs finite theta > 0 and finite mu");
     if (sz) {
@@ -115,7 +130,8 @@ int validate(const lbm_params *p, lbm_t h, Sizes *sz)
         sz->state = (size_t)Q * (size_t)sz->stride * elem_size(p->storage);
         sz->adjoint = (size_t)Q * (size_t)sz->stride * sizeof(float);
         const size_t parts = std::max((size_t)kReduceBlocks * 5, (size_t)sz->nblocks * 4);
-        sz->work = 64 + parts * sizeof(double);
+        sz->work = 64 + parts * sizeof(double) + (size_t)kReduceStage * 8 * sizeof(double);
+        sz->work = (sz->work + 255) / 256 * 256 + (size_t)sz->stride * 4;  // link masks
     }
     return LBM_OK;
 }
@@ -147,6 +163,16 @@ void fill_physics(lbm_t h)
     }
     ph.A = (float)k.A;
     ph.Bc = (float)k.Bc;
+    for (int s = 0; s < 4; ++s) ph.C2[s] = (float)(2.0 * k.C[s]);
+    {
+        int Q = 0, D = 0, e[3 * kQMax];
+        lbm_lattice_info(h->p.lattice, &Q, &D, e);
+        for (int q = 0; q < Q; ++q) {
+            const double eE = (e[3 * q] * h->p.E[0] + e[3 * q + 1] * h->p.E[1] + e[3 * q + 2] * h->p.E[2]) / k.cs;
+            ph.c1q[q] = (float)(k.A * eE);
+            ph.c2q[q] = (float)(2.0 * k.Bc * eE);
+        }
+    }
     ph.cs = (float)k.cs;
     ph.inv_cs2 = (float)(1.0 / (k.cs * k.cs));
     for (int i = 0; i < 3; ++i) {
@@ -163,9 +189,26 @@ void fill_physics(lbm_t h)
 }
 
 bool has_B(const lbm_t h) { return h->p.B[0] != 0.0 || h->p.B[1] != 0.0 || h->p.B[2] != 0.0; }
+bool has_E(const lbm_t h) { return h->p.E[0] != 0.0 || h->p.E[1] != 0.0 || h->p.E[2] != 0.0; }
+int force_level(const lbm_t h) { return has_B(h) ? 2 : (has_E(h) ? 1 : 0); }
+const void *links_of(const lbm_t h) { return h->mask ? h->links : nullptr; }
 
 double *work_out(lbm_t h) { return reinterpret_cast<double *>(h->work); }
 double *work_parts(lbm_t h) { return reinterpret_cast<double *>(h->work + 64); }
+// link masks after the reduction scratch (256-byte aligned)
+void *work_links(lbm_t h)
+{
+    const size_t parts = std::max((size_t)kReduceBlocks * 5, (size_t)h->g.nblocks * 4);
+    size_t off = 64 + parts * sizeof(double) + (size_t)kReduceStage * 8 * sizeof(double);
+    off = (off + 255) / 256 * 256;
+    return h->work + off;
+}
+// second-stage scratch after the largest partials array
+double *work_stage(lbm_t h)
+{
+    const size_t parts = std::max((size_t)kReduceBlocks * 5, (size_t)h->g.nblocks * 4);
+    return reinterpret_cast<double *>(h->work + 64 + parts * sizeof(double));
+}
 
 }  // namespace
 
@@ -275,6 +318,14 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *s
     h->g.mask = mask;
     h->g.s = s;
     fill_physics(h);
+    h->links = work_links(h);
+    if (mask) {
+        const hipError_t e = launch_links(p->lattice, h->g, h->links, h->stream);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(nullptr, LBM_EDEVICE, "link mask kernel launch: %s", hipGetErrorString(e));
+        }
+    }
     *out = h;
     return LBM_OK;
 }
@@ -305,11 +356,13 @@ int lbm_step(lbm_t h, int nsteps)
     StepArgs a{};
     a.g = h->g;
     a.ph = h->ph;
-    const bool mag = has_B(h);
+    a.links = links_of(h);
+    a.remap = use_xcd_remap(h->p.lattice, h->mask != nullptr, h->s != nullptr);
+    const int force = force_level(h);
     for (int t = 0; t < nsteps; ++t) {
         a.src = h->buf[h->cur];
         a.dst = h->buf[h->cur ^ 1];
-        const hipError_t e = launch_step(h->p.lattice, h->p.storage, mag, a, h->stream);
+        const hipError_t e = launch_step(h->p.lattice, h->p.storage, force, a, h->stream);
         if (e != hipSuccess) return hip_fail(h, e, "step kernel launch");
         h->cur ^= 1;
     }
@@ -323,9 +376,11 @@ int lbm_step_from(lbm_t h, const void *src, void *dst)
     StepArgs a{};
     a.g = h->g;
     a.ph = h->ph;
+    a.links = links_of(h);
+    a.remap = use_xcd_remap(h->p.lattice, h->mask != nullptr, h->s != nullptr);
     a.src = src;
     a.dst = dst;
-    const hipError_t e = launch_step(h->p.lattice, h->p.storage, has_B(h), a, h->stream);
+    const hipError_t e = launch_step(h->p.lattice, h->p.storage, force_level(h), a, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "step kernel launch");
     return LBM_OK;
 }
@@ -335,6 +390,7 @@ static int gather_common(lbm_t h, const void *state, float *rho, float *u, doubl
     GatherArgs a{};
     a.g = h->g;
     a.ph = h->ph;
+    a.links = links_of(h);
     a.src = state ? state : h->buf[h->cur];
     a.rho = rho;
     a.u = u;
@@ -370,7 +426,7 @@ int lbm_current(lbm_t h, double out[4])
     if (!h->initialized) return fail(h, LBM_ESTATE, "lbm_current before lbm_init or lbm_set_state");
     int rc = gather_common(h, nullptr, nullptr, nullptr, nullptr, work_parts(h));
     if (rc != LBM_OK) return rc;
-    hipError_t e = launch_reduce_final(work_parts(h), kReduceBlocks, 5, work_out(h), 0, h->stream);
+    hipError_t e = launch_reduce_final(work_parts(h), kReduceBlocks, 5, work_out(h), 0, h->stream, work_stage(h));
     if (e != hipSuccess) return hip_fail(h, e, "reduce kernel launch");
     double tot[5];
     e = hipMemcpyAsync(tot, work_out(h), sizeof(tot), hipMemcpyDeviceToHost, h->stream);
@@ -454,6 +510,8 @@ int lbm_adjoint_step(lbm_t h, const void *state, const float *lam_in, float *lam
     AdjointArgs a{};
     a.g = h->g;
     a.ph = h->ph;
+    a.links = links_of(h);
+    a.remap = use_xcd_remap(h->p.lattice, h->mask != nullptr, h->s != nullptr);
     a.state = state;
     a.lam_in = lam_in;
     a.lam_out = lam_out;
@@ -462,7 +520,7 @@ int lbm_adjoint_step(lbm_t h, const void *state, const float *lam_in, float *lam
     hipError_t e = launch_adjoint(h->p.lattice, h->p.storage, has_B(h), a, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "adjoint kernel launch");
     if (grad_scalars) {
-        e = launch_reduce_final(work_parts(h), h->g.nblocks, 4, grad_scalars, 1, h->stream);
+        e = launch_reduce_final(work_parts(h), h->g.nblocks, 4, grad_scalars, 1, h->stream, work_stage(h));
         if (e != hipSuccess) return hip_fail(h, e, "reduce kernel launch");
     }
     return LBM_OK;

@@ -49,6 +49,8 @@ struct Geometry {
     const float *s;       // nullable
 };
 
+constexpr int kQMax = 19;
+
 struct Physics {
     float rho0;
     float omega;      // 1 / tau
@@ -57,16 +59,21 @@ struct Physics {
                       // sum_a lam_a e_a e_a = identity holds exactly in FP32 constants
     float A, Bc;      // reduced EDF coefficients
     float C[4];       // C_k (source term)
+    float C2[4];      // 2 C_k
     float Cp[4];      // C_k c_s^2 (equilibrium, U = u / c_s)
     float cs, inv_cs2;
     float E[3];       // xi-units per step
     float B[3];
+    float c1q[kQMax]; // A (e_q.E) / c_s, library velocity order
+    float c2q[kQMax]; // 2 Bc (e_q.E) / c_s
     float scale, inv_scale;  // storage scale (F16: 2^k), 1 otherwise
 };
 
 struct StepArgs {
     Geometry g;
     Physics ph;
+    int remap;          // XCD-contiguous block order
+    const void *links;  // per-node link masks (nullable: no solids)
     const void *src;
     void *dst;
 };
@@ -82,6 +89,7 @@ struct InitArgs {
 struct GatherArgs {
     Geometry g;
     Physics ph;
+    const void *links;
     const void *src;
     float *rho;       // nullable
     float *u;         // nullable
@@ -94,6 +102,8 @@ struct GatherArgs {
 struct AdjointArgs {
     Geometry g;
     Physics ph;
+    int remap;
+    const void *links;
     const void *state;
     const float *lam_in;
     float *lam_out;
@@ -102,12 +112,20 @@ struct AdjointArgs {
 };
 
 // Launchers (lbm_kernels.hip). Each returns hipSuccess or the launch error.
-hipError_t launch_step(int lattice, int storage, bool mag, const StepArgs &a, hipStream_t st);
+// force: 0 no field, 1 E only, 2 E and B.
+hipError_t launch_step(int lattice, int storage, int force, const StepArgs &a, hipStream_t st);
+// Per-node link masks from g.mask into links (link_mask_bytes(lattice) per node).
+hipError_t launch_links(int lattice, const Geometry &g, void *links, hipStream_t st);
+size_t link_mask_bytes(int lattice);
 hipError_t launch_init(int lattice, int storage, const InitArgs &a, hipStream_t st);
 hipError_t launch_gather(int lattice, int storage, const GatherArgs &a, int nblocks_reduce,
                          hipStream_t st);
+// Sum per-block partials [nparts][ncomp] (ncomp <= 8) into out (+= if accumulate).
+// `stage` (kReduceStage * ncomp doubles, nullable) enables a two-stage reduction.
 hipError_t launch_reduce_final(const double *partials, int nparts, int ncomp, double *out,
-                               int accumulate, hipStream_t st);
+                               int accumulate, hipStream_t st, double *stage);
+int step_vector_width(int lattice, int storage, int nx);
+int use_xcd_remap(int lattice, bool mask, bool soft);
 hipError_t launch_adjoint(int lattice, int storage, bool mag, const AdjointArgs &a, hipStream_t st);
 hipError_t launch_seed(int lattice, const Geometry &g, float value_per_unit_e, int axis, float *lam,
                        hipStream_t st);
@@ -118,5 +136,6 @@ int compute_constants(const lbm_params *p, lbm_constants *k);
 
 constexpr int kBlock = 256;        // threads per block of the node kernels
 constexpr int kReduceBlocks = 1024;  // blocks of the gather/reduce kernel
+constexpr int kReduceStage = 256;    // blocks of the first stage of a partials reduction
 
 }  // namespace lbm

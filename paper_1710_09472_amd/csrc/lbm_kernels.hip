@@ -1,23 +1,61 @@
 // lbm_kernels.hip -- gfx950 kernels of the semiclassical lattice Boltzmann step.
 //
-// One thread per lattice node, 256 threads (4 wave64) per block along x. The state
-// holds post-collision populations of the previous step as structure-of-arrays
-// deviations d_a = f_a - what_a rho0 (FP32, FP16 x 2^k or BF16); a step pulls
-// f_a(x) = g_a(x - e_a) from the neighbours (misaligned by at most one element in x,
-// whole rows in y and z), or g_abar(x) when x - e_a is solid (halfway bounce-back),
-// collides in FP32 registers and writes its own node's Q values to the other buffer:
-// every population is read once and written once per step.
+// Layout: the state holds the post-collision populations of the previous step as
+// structure-of-arrays deviations d_a = f_a - what_a rho0 (FP32, FP16 x 2^k or BF16),
+// array a at offset a*stride, node n = x + nx*(y + ny*z). A step pulls
+// f_a(x) = g_a(x - e_a) from the neighbours, or g_abar(x) when x - e_a is solid
+// (halfway bounce-back), collides in FP32 registers and writes the node's Q values to
+// the other buffer: every population is read once and written once per step.
 //
-// The block index is remapped so that each of the 8 XCDs (which receive blocks
-// round-robin) works on one contiguous slab of the grid; neighbouring tiles, whose
-// x-halo cache lines overlap, then share an L2.
+// Launch: 256 threads (4 wave64) per block; each thread owns V consecutive nodes of a
+// row (V = 1, 2 or 4), so the arrays are read and written with V-wide vector accesses;
+// the one value of an x-shifted population that falls outside the thread's V nodes is
+// fetched with a scalar load (it lies in a neighbouring lane's cache line). All loads of
+// a thread are issued before any arithmetic. Blocks are remapped so that each of the 8
+// XCDs (which receive blocks round-robin) works on one contiguous slab of the grid.
+// Solid nodes are described by a per-node link mask built once: bit a set when
+// x - e_a is solid, top bit set when x itself is solid.
 #include "lbm_internal.h"
 
+#include <cstdlib>
+
+#ifndef LBM_NT_STORE
+#define LBM_NT_STORE 1
+#endif
+
 namespace lbm {
+
+static int env_int(const char *name, int dflt)
+{
+    const char *e = std::getenv(name);
+    return e ? std::atoi(e) : dflt;
+}
+
+// Nodes per thread of the step kernel (measured on MI355X): 1 for FP32 and for D3V19,
+// 2 for 16-bit D2V9; halved until it divides nx. LBM_STEP_VEC=1|2|4 overrides it.
+int step_vector_width(int lattice, int storage, int nx)
+{
+    static const int forced = env_int("LBM_STEP_VEC", 0);
+    int v = forced;
+    if (v != 1 && v != 2 && v != 4) v = (storage != LBM_F32 && lattice == LBM_D2V9) ? 2 : 1;
+    while (v > 1 && nx % v) v >>= 1;
+    return v;
+}
+
+// XCD-contiguous block order (measured on MI355X): it pays off where the reads of a node
+// span several rows of solids or planes (D3V19, masks, porosity fields) and costs ~8 %
+// on the plain D2V9 grid, which keeps the hardware order. LBM_XCD_REMAP=0|1 overrides.
+int use_xcd_remap(int lattice, bool mask, bool soft)
+{
+    static const int forced = env_int("LBM_XCD_REMAP", -1);
+    if (forced == 0 || forced == 1) return forced;
+    return (lattice == LBM_D3V19 || mask || soft) ? 1 : 0;
+}
+
 namespace {
 
 // ---------------------------------------------------------------------------------
-// Storage codecs: deviation <-> stored value.
+// Storage codecs: deviation <-> stored value (round to nearest even).
 // ---------------------------------------------------------------------------------
 template <int ST>
 struct Codec;
@@ -32,124 +70,99 @@ struct Codec<LBM_F32> {
 template <>
 struct Codec<LBM_F16> {
     using T = _Float16;
-    // value = d * 2^k: the scale is a power of two, so scaling is exact
+    // stored value = d * 2^k; the scale is a power of two, so scaling is exact
     static __device__ __forceinline__ float dec(T v, float inv_scale) { return (float)v * inv_scale; }
-    static __device__ __forceinline__ T enc(float f, float scale) { return (T)(f * scale); }  // RNE
+    static __device__ __forceinline__ T enc(float f, float scale) { return (T)(f * scale); }
 };
 
 template <>
 struct Codec<LBM_BF16> {
-    using T = uint16_t;
-    static __device__ __forceinline__ float dec(T v, float) { return __uint_as_float(((uint32_t)v) << 16); }
-    static __device__ __forceinline__ T enc(float f, float)
-    {
-        uint32_t u = __float_as_uint(f);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return (T)((u >> 16) | 0x0040u);  // keep NaN a NaN
-        u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest, ties to even
-        return (T)(u >> 16);
-    }
+    using T = __bf16;
+    static __device__ __forceinline__ float dec(T v, float) { return (float)v; }
+    static __device__ __forceinline__ T enc(float f, float) { return (T)f; }
 };
 
-// Block -> contiguous slab per XCD (blocks are dealt to the 8 XCDs round-robin).
-__device__ __forceinline__ int xcd_remap(int bid, int nb)
-{
-    const int per = nb >> 3, rem = nb & 7;
-    const int xcd = bid & 7, k = bid >> 3;
-    return xcd * per + min(xcd, rem) + k;
-}
-
-struct Node {
-    int x, y, z, n;
+template <int ST, int V>
+struct VecT {
+    typedef typename Codec<ST>::T type __attribute__((ext_vector_type(V)));
+};
+template <int ST>
+struct VecT<ST, 1> {
+    using type = typename Codec<ST>::T;
 };
 
-// Node of this thread, or n = -1 past the end of a row.
-__device__ __forceinline__ Node node_of_thread(const Geometry &g, bool remap)
+template <int ST, int V>
+__device__ __forceinline__ void vload(const typename Codec<ST>::T *p, float inv_scale, float *f)
 {
-    const int bid = remap ? xcd_remap((int)blockIdx.x, g.nblocks) : (int)blockIdx.x;
-    const int row = bid / g.ntx;
-    Node nd;
-    nd.x = (bid - row * g.ntx) * kBlock + (int)threadIdx.x;
-    nd.y = row % g.ny;
-    nd.z = row / g.ny;
-    nd.n = nd.x < g.nx ? nd.x + g.nx * row : -1;
-    return nd;
-}
-
-__device__ __forceinline__ int wrapm(int i, int n) { return i == 0 ? n - 1 : i - 1; }
-__device__ __forceinline__ int wrapp(int i, int n) { return i == n - 1 ? 0 : i + 1; }
-
-// Pull the pre-collision deviations of node nd from the post-collision state.
-template <int LAT, int ST, bool MASK>
-__device__ __forceinline__ void gather(const Geometry &g, const typename Codec<ST>::T *__restrict__ src,
-                                       float inv_scale, const Node &nd, float *d)
-{
-    using L = Lat<LAT>;
-    const int xm = wrapm(nd.x, g.nx), xp = wrapp(nd.x, g.nx);
-    const int ym = wrapm(nd.y, g.ny), yp = wrapp(nd.y, g.ny);
-    const int zm = wrapm(nd.z, g.nz), zp = wrapp(nd.z, g.nz);
+    if constexpr (V == 1) {
+        f[0] = Codec<ST>::dec(*p, inv_scale);
+    } else {
+        using VT = typename VecT<ST, V>::type;
+        const VT v = *reinterpret_cast<const VT *>(p);
 #pragma unroll
-    for (int q = 0; q < L::Q; ++q) {
-        const int sx = L::ex[q] > 0 ? xm : (L::ex[q] < 0 ? xp : nd.x);
-        const int sy = L::ey[q] > 0 ? ym : (L::ey[q] < 0 ? yp : nd.y);
-        const int sz = L::ez[q] > 0 ? zm : (L::ez[q] < 0 ? zp : nd.z);
-        const int sn = sx + g.nx * (sy + g.ny * sz);
-        int idx = q * g.stride + sn;
-        if (MASK && q != 0) {
-            if (g.mask[sn]) idx = L::opp[q] * g.stride + nd.n;
-        }
-        d[q] = Codec<ST>::dec(src[idx], inv_scale);
+        for (int i = 0; i < V; ++i) f[i] = Codec<ST>::dec(v[i], inv_scale);
     }
 }
 
-// Macroscopic quantities from pre-collision deviations:
-// drho = sum d, rho = rho0 + drho, U = u / c_s = (sum d e) / (rho c_s^2).
-template <int LAT>
-struct Macro {
-    float drho, rho, j[3], U[3], U2;  // j = sum d e (lattice units), U = j / (rho c_s^2)
-};
-
-template <int LAT>
-__device__ __forceinline__ Macro<LAT> macro(const Physics &p, const float *d)
+template <int ST, int V>
+__device__ __forceinline__ void vstore(typename Codec<ST>::T *p, float scale, const float *f)
 {
-    using L = Lat<LAT>;
-    Macro<LAT> m;
-    float r = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+    if constexpr (V == 1) {
+        const typename Codec<ST>::T v = Codec<ST>::enc(f[0], scale);
+#if LBM_NT_STORE
+        __builtin_nontemporal_store(v, p);
+#else
+        *p = v;
+#endif
+    } else {
+        using VT = typename VecT<ST, V>::type;
+        VT v;
 #pragma unroll
-    for (int q = 0; q < L::Q; ++q) {
-        r += d[q];
-        if (L::ex[q]) jx += L::ex[q] * d[q];
-        if (L::ey[q]) jy += L::ey[q] * d[q];
-        if (L::ez[q]) jz += L::ez[q] * d[q];
+        for (int i = 0; i < V; ++i) v[i] = Codec<ST>::enc(f[i], scale);
+#if LBM_NT_STORE
+        __builtin_nontemporal_store(v, reinterpret_cast<VT *>(p));
+#else
+        *reinterpret_cast<VT *>(p) = v;
+#endif
     }
-    m.drho = r;
-    m.rho = p.rho0 + r;
-    m.j[0] = jx;
-    m.j[1] = jy;
-    m.j[2] = jz;
-    const float k = p.inv_cs2 / m.rho;
-    m.U[0] = jx * k;
-    m.U[1] = jy * k;
-    m.U[2] = jz * k;
-    m.U2 = m.U[0] * m.U[0] + m.U[1] * m.U[1] + m.U[2] * m.U[2];
-    return m;
 }
 
-template <int LAT, int q>
-__device__ __forceinline__ float edot(const float *v)
-{
-    using L = Lat<LAT>;
-    float r = 0.f;
-    if (L::ex[q]) r += L::ex[q] * v[0];
-    if (L::ey[q]) r += L::ey[q] * v[1];
-    if (L::ez[q]) r += L::ez[q] * v[2];
-    return r;
-}
-
+// ---------------------------------------------------------------------------------
+// Lattice helpers (all indices compile-time after unrolling).
+// ---------------------------------------------------------------------------------
 template <int LAT, int q>
 __device__ __forceinline__ constexpr int shell()
 {
     using L = Lat<LAT>;
     return L::ex[q] * L::ex[q] + L::ey[q] * L::ey[q] + L::ez[q] * L::ez[q];
+}
+
+// e_q . v without adding zeros (0 + x cannot be folded in IEEE arithmetic).
+template <int LAT, int q>
+__device__ __forceinline__ float edot(const float *v)
+{
+    using L = Lat<LAT>;
+    constexpr int a = L::ex[q], b = L::ey[q], c = L::ez[q];
+    if constexpr (a == 0 && b == 0 && c == 0) {
+        return 0.f;
+    } else {
+        float r = 0.f;
+        bool first = true;
+        if constexpr (a != 0) {
+            r = a > 0 ? v[0] : -v[0];
+            first = false;
+        }
+        if constexpr (b != 0) {
+            const float t = b > 0 ? v[1] : -v[1];
+            r = first ? t : r + t;
+            first = false;
+        }
+        if constexpr (c != 0) {
+            const float t = c > 0 ? v[2] : -v[2];
+            r = first ? t : r + t;
+        }
+        return r;
+    }
 }
 
 // Unrolled compile-time loop over q.
@@ -162,12 +175,340 @@ __device__ __forceinline__ void for_q(F &&f)
     }
 }
 
-// Equilibrium deviation of a moving population q != 0 (reduced EDF of Sec. 9.1):
-//   deq_q = what_k drho + lam_k (e.j) + what_k rho (Bc (e.U)^2 + C_k c_s^2 U^2),
-// where lam_k (e.j) = what_k rho A (e.U). Written with e.j and weights lam_k whose
-// second moment is exactly the identity, the equilibrium carries exactly the momentum
-// j of the node: FP32 rounding of the constants then cannot bias momentum relaxation.
-// The rest population is closed by mass conservation, deq_0 = drho - sum_(q != 0) deq_q.
+template <int LAT>
+struct LinkMask;
+template <>
+struct LinkMask<LBM_D2V9> {
+    using T = uint16_t;
+    static constexpr T solid = (T)0x8000u;
+};
+template <>
+struct LinkMask<LBM_D3V19> {
+    using T = uint32_t;
+    static constexpr T solid = 0x80000000u;
+};
+
+// ---------------------------------------------------------------------------------
+// Thread -> nodes.
+// ---------------------------------------------------------------------------------
+// Block -> contiguous slab per XCD.
+__device__ __forceinline__ int xcd_remap(int bid, int nb)
+{
+    const int per = nb >> 3, rem = nb & 7;
+    const int xcd = bid & 7, k = bid >> 3;
+    return xcd * per + min(xcd, rem) + k;
+}
+
+__device__ __forceinline__ int wrapm(int i, int n) { return i == 0 ? n - 1 : i - 1; }
+__device__ __forceinline__ int wrapp(int i, int n) { return i == n - 1 ? 0 : i + 1; }
+
+struct Tile {
+    int x0, y, z;  // first node of this thread (clamped into the row)
+    int own;       // node index of x0
+    bool valid;    // the thread owns nodes
+};
+
+template <int V>
+__device__ __forceinline__ Tile tile_of(const Geometry &g, int bid, int ntx)
+{
+    const int row = bid / ntx;
+    Tile t;
+    int x0 = ((bid - row * ntx) * kBlock + (int)threadIdx.x) * V;
+    t.valid = x0 < g.nx;
+    if (!t.valid) x0 = g.nx - V;
+    t.x0 = x0;
+    t.y = row % g.ny;
+    t.z = row / g.ny;
+    t.own = x0 + g.nx * row;
+    return t;
+}
+
+// Pull the pre-collision deviations of the V nodes of tile t; lk holds their link masks.
+template <int LAT, int ST, bool MASK, int V>
+__device__ __forceinline__ void gather_tile(const Geometry &g, const typename Codec<ST>::T *__restrict__ src,
+                                            float inv_scale, const Tile &t,
+                                            const typename LinkMask<LAT>::T *lk, float (&d)[V][Lat<LAT>::Q])
+{
+    using L = Lat<LAT>;
+    const int nx = g.nx;
+    const int ym = wrapm(t.y, g.ny), yp = wrapp(t.y, g.ny);
+    const int zm = wrapm(t.z, g.nz), zp = wrapp(t.z, g.nz);
+    const int xl = t.x0 == 0 ? nx - 1 : t.x0 - 1;
+    const int xr = t.x0 + V >= nx ? 0 : t.x0 + V;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+        const int sy = L::ey[q] > 0 ? ym : (L::ey[q] < 0 ? yp : t.y);
+        const int sz = L::ez[q] > 0 ? zm : (L::ez[q] < 0 ? zp : t.z);
+        const typename Codec<ST>::T *base = src + q * g.stride + nx * (sy + g.ny * sz);
+        if (L::ex[q] == 0) {
+            float f[V];
+            vload<ST, V>(base + t.x0, inv_scale, f);
+#pragma unroll
+            for (int i = 0; i < V; ++i) d[i][q] = f[i];
+        } else if (V == 1) {
+            d[0][q] = Codec<ST>::dec(base[L::ex[q] > 0 ? xl : xr], inv_scale);
+        } else if (L::ex[q] > 0) {  // from x - 1
+            float f[V];
+            vload<ST, V>(base + t.x0, inv_scale, f);
+            d[0][q] = Codec<ST>::dec(base[xl], inv_scale);
+#pragma unroll
+            for (int i = 1; i < V; ++i) d[i][q] = f[i - 1];
+        } else {  // from x + 1
+            float f[V];
+            vload<ST, V>(base + t.x0, inv_scale, f);
+#pragma unroll
+            for (int i = 0; i < V - 1; ++i) d[i][q] = f[i + 1];
+            d[V - 1][q] = Codec<ST>::dec(base[xr], inv_scale);
+        }
+    }
+    if (MASK) {
+        // one branch for the whole tile: most tiles have no solid neighbour at all
+        typename LinkMask<LAT>::T any = 0;
+#pragma unroll
+        for (int i = 0; i < V; ++i) any |= lk[i] & (typename LinkMask<LAT>::T)~LinkMask<LAT>::solid;
+        if (any) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+#pragma unroll
+                for (int q = 1; q < L::Q; ++q)
+                    if ((lk[i] >> q) & 1u)
+                        d[i][q] = Codec<ST>::dec(src[L::opp[q] * g.stride + t.own + i], inv_scale);
+            }
+        }
+    }
+}
+
+template <int LAT, int V>
+__device__ __forceinline__ void load_links(const typename LinkMask<LAT>::T *links, int own,
+                                           typename LinkMask<LAT>::T (&lk)[V])
+{
+    using LT = typename LinkMask<LAT>::T;
+    if constexpr (V == 1) {
+        lk[0] = links[own];
+    } else {
+        typedef LT VT __attribute__((ext_vector_type(V)));
+        const VT v = *reinterpret_cast<const VT *>(links + own);
+#pragma unroll
+        for (int i = 0; i < V; ++i) lk[i] = v[i];
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Collision of one node in deviation form: the discrete BGK update of Sec. 9.1 with the
+// reduced second-order EDF and the Lorentz source of Sec. 7, then the optional partial
+// bounce-back.
+//   rho = rho0 + drho, drho = sum d, j = sum d e, U = u / c_s = j / (rho c_s^2);
+//   deq_q = what_k drho + lam_k (e.j) + what_k rho (Bc (e.U)^2 + C_k c_s^2 U^2), q != 0,
+//           lam_k (e.j) = what_k rho A (e.U) with lam weights whose second moment is
+//           exactly the identity: the equilibrium carries exactly the node's momentum;
+//   deq_0 = drho - sum_(q != 0) deq_q (mass closure);
+//   sigma_q = (e.E / c_s)(A + 2 Bc e.U) + 2 C_k (c_s U.E + e.(B x U));
+//   d*_q = d_q + omega (deq_q - d_q) + rho what_k sigma_q;
+//   g_q = (1 - s) d*_q + s d_qbar.
+// FORCE: 0 no field, 1 E only, 2 E and B.
+// ---------------------------------------------------------------------------------
+template <int LAT>
+struct Macro {
+    float drho, rho, j[3], U[3], U2;
+};
+
+template <int LAT>
+__device__ __forceinline__ Macro<LAT> macro(const Physics &p, const float *d)
+{
+    using L = Lat<LAT>;
+    Macro<LAT> m;
+    float r = d[0];
+#pragma unroll
+    for (int q = 1; q < L::Q; ++q) r += d[q];
+    float j[3] = {0.f, 0.f, 0.f};
+    bool fx = true, fy = true, fz = true;
+#pragma unroll
+    for (int q = 1; q < L::Q; ++q) {
+        if (L::ex[q]) {
+            const float t = L::ex[q] > 0 ? d[q] : -d[q];
+            j[0] = fx ? t : j[0] + t;
+            fx = false;
+        }
+        if (L::ey[q]) {
+            const float t = L::ey[q] > 0 ? d[q] : -d[q];
+            j[1] = fy ? t : j[1] + t;
+            fy = false;
+        }
+        if (L::ez[q]) {
+            const float t = L::ez[q] > 0 ? d[q] : -d[q];
+            j[2] = fz ? t : j[2] + t;
+            fz = false;
+        }
+    }
+    m.drho = r;
+    m.rho = p.rho0 + r;
+    const float k = p.inv_cs2 * __builtin_amdgcn_rcpf(m.rho);
+    m.j[0] = j[0];
+    m.j[1] = j[1];
+    m.j[2] = j[2];
+    m.U[0] = j[0] * k;
+    m.U[1] = j[1] * k;
+    if constexpr (L::D == 3) {
+        m.U[2] = j[2] * k;
+        m.U2 = m.U[0] * m.U[0] + m.U[1] * m.U[1] + m.U[2] * m.U[2];
+    } else {
+        m.U[2] = 0.f;
+        m.U2 = m.U[0] * m.U[0] + m.U[1] * m.U[1];
+    }
+    return m;
+}
+
+template <int LAT, int FORCE>
+__device__ __forceinline__ void collide_node(const Physics &p, const Macro<LAT> &m, const float *d, float *o,
+                                             float *deq_out = nullptr, float *sig_out = nullptr)
+{
+    using L = Lat<LAT>;
+    const float om = p.omega;
+    float wd[3], wr[3], cu[3], sk[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        wd[k] = p.what[k] * m.drho;
+        wr[k] = p.what[k] * m.rho;
+        cu[k] = p.Cp[k] * m.U2;
+    }
+    float W[3] = {0.f, 0.f, 0.f};
+    if constexpr (FORCE >= 1) {
+        float UE = m.U[0] * p.E[0] + m.U[1] * p.E[1];
+        if constexpr (L::D == 3) UE += m.U[2] * p.E[2];
+        UE *= p.cs;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sk[k] = p.C2[k] * UE;
+    }
+    if constexpr (FORCE == 2) {
+        W[0] = p.B[1] * m.U[2] - p.B[2] * m.U[1];
+        W[1] = p.B[2] * m.U[0] - p.B[0] * m.U[2];
+        W[2] = p.B[0] * m.U[1] - p.B[1] * m.U[0];
+    }
+    float sum_eq = 0.f;
+    for_q<L::Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        if constexpr (q != 0) {
+            constexpr int k = shell<LAT, q>();
+            const float eu = edot<LAT, q>(m.U);
+            const float ej = edot<LAT, q>(m.j);
+            const float quad = __builtin_fmaf(p.Bc * eu, eu, cu[k]);
+            const float deq = __builtin_fmaf(wr[k], quad, __builtin_fmaf(p.lam[k], ej, wd[k]));
+            sum_eq = (q == 1) ? deq : sum_eq + deq;
+            float v = __builtin_fmaf(om, deq - d[q], d[q]);
+            if constexpr (FORCE >= 1) {
+                float sig = __builtin_fmaf(p.c2q[q], eu, p.c1q[q] + sk[k]);
+                if constexpr (FORCE == 2) sig = __builtin_fmaf(p.C2[k], edot<LAT, q>(W), sig);
+                v = __builtin_fmaf(wr[k], sig, v);
+                if (sig_out) sig_out[q] = sig;
+            }
+            o[q] = v;
+            if (deq_out) deq_out[q] = deq;
+        }
+    });
+    const float deq0 = m.drho - sum_eq;
+    float v0 = __builtin_fmaf(om, deq0 - d[0], d[0]);
+    if constexpr (FORCE >= 1) {
+        v0 = __builtin_fmaf(wr[0], sk[0], v0);
+        if (sig_out) sig_out[0] = sk[0];
+    }
+    o[0] = v0;
+    if (deq_out) deq_out[0] = deq0;
+}
+
+template <int LAT, bool SOFT, int FORCE>
+__device__ __forceinline__ void collide(const Physics &p, const float *d, float s, float *o)
+{
+    using L = Lat<LAT>;
+    const Macro<LAT> m = macro<LAT>(p, d);
+    collide_node<LAT, FORCE>(p, m, d, o);
+    if (SOFT) {
+        float t[L::Q];
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) t[q] = __builtin_fmaf(s, d[L::opp[q]] - o[q], o[q]);
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) o[q] = t[q];
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// K1: fused pull-stream + collide + force + partial bounce-back.
+// ---------------------------------------------------------------------------------
+template <int LAT, int ST, bool MASK, bool SOFT, int FORCE, int V>
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs a, int ntx, int nblocks)
+{
+    using L = Lat<LAT>;
+    using T = typename Codec<ST>::T;
+    using LT = typename LinkMask<LAT>::T;
+    const int bid = a.remap ? xcd_remap((int)blockIdx.x, nblocks) : (int)blockIdx.x;
+    const Tile t = tile_of<V>(a.g, bid, ntx);
+    LT lk[V];
+    bool fluid[V];
+    bool all_fluid = true;
+    if (MASK) {
+        load_links<LAT, V>(static_cast<const LT *>(a.links), t.own, lk);
+        bool any_fluid = false;
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            fluid[i] = !(lk[i] & LinkMask<LAT>::solid);
+            any_fluid = any_fluid || fluid[i];
+            all_fluid = all_fluid && fluid[i];
+        }
+        if (!any_fluid) return;
+    }
+    float d[V][L::Q];
+    gather_tile<LAT, ST, MASK, V>(a.g, static_cast<const T *>(a.src), a.ph.inv_scale, t, lk, d);
+    float sv[V];
+    if (SOFT) vload<LBM_F32, V>(a.g.s + t.own, 1.f, sv);
+    float o[V][L::Q];
+#pragma unroll
+    for (int i = 0; i < V; ++i) collide<LAT, SOFT, FORCE>(a.ph, d[i], SOFT ? sv[i] : 0.f, o[i]);
+    if (!t.valid) return;
+    T *__restrict__ dst = static_cast<T *>(a.dst);
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+        T *p = dst + q * a.g.stride + t.own;
+        if (!MASK || all_fluid) {
+            float f[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) f[i] = o[i][q];
+            vstore<ST, V>(p, a.ph.scale, f);
+        } else {
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+                if (fluid[i]) p[i] = Codec<ST>::enc(o[i][q], a.ph.scale);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Link masks from the solid mask: bit q when x - e_q is solid, top bit when x is.
+// ---------------------------------------------------------------------------------
+template <int LAT>
+__global__ __launch_bounds__(kBlock) void k_links(Geometry g, typename LinkMask<LAT>::T *links)
+{
+    using L = Lat<LAT>;
+    using LT = typename LinkMask<LAT>::T;
+    const Tile t = tile_of<1>(g, (int)blockIdx.x, g.ntx);
+    if (!t.valid) return;
+    const int xm = wrapm(t.x0, g.nx), xp = wrapp(t.x0, g.nx);
+    const int ym = wrapm(t.y, g.ny), yp = wrapp(t.y, g.ny);
+    const int zm = wrapm(t.z, g.nz), zp = wrapp(t.z, g.nz);
+    LT bits = g.mask[t.own] ? LinkMask<LAT>::solid : (LT)0;
+#pragma unroll
+    for (int q = 1; q < L::Q; ++q) {
+        const int sx = L::ex[q] > 0 ? xm : (L::ex[q] < 0 ? xp : t.x0);
+        const int sy = L::ey[q] > 0 ? ym : (L::ey[q] < 0 ? yp : t.y);
+        const int sz = L::ez[q] > 0 ? zm : (L::ez[q] < 0 ? zp : t.z);
+        if (g.mask[sx + g.nx * (sy + g.ny * sz)]) bits |= (LT)(1u << q);
+    }
+    links[t.own] = bits;
+}
+
+// ---------------------------------------------------------------------------------
+// K2: initial state. The stored state is post-collision, so node x holds, for each q,
+// the value that the next pull delivers: f^eq_q(x + e_q) when x + e_q is fluid, or
+// f^eq_qbar(x) when it is solid (bounced back).
+// ---------------------------------------------------------------------------------
 template <int LAT, int q>
 __device__ __forceinline__ float deq_moving(const Physics &p, float drho, float rho, const float *j,
                                             const float *U, float U2, float sign = 1.f)
@@ -178,104 +519,25 @@ __device__ __forceinline__ float deq_moving(const Physics &p, float drho, float 
     return p.what[k] * drho + p.lam[k] * ej + p.what[k] * rho * (p.Bc * eu * eu + p.Cp[k] * U2);
 }
 
-// Post-collision values of one node (deviation form), before partial bounce-back:
-//   d*_q = d_q + omega (deq_q - d_q) + rho what_q sigma_q,
-//   sigma_q = (e.E / c_s)(A + 2 Bc e.U) + 2 C_k (c_s U.E + e.(B x U))   (source of Sec. 7).
-// deq (optional) receives the equilibrium deviations.
-template <int LAT, bool MAG>
-__device__ __forceinline__ void collide_bgk(const Physics &p, const Macro<LAT> &m, const float *d, float *o,
-                                            float *deq_out = nullptr)
-{
-    using L = Lat<LAT>;
-    const float UE = p.cs * (m.U[0] * p.E[0] + m.U[1] * p.E[1] + m.U[2] * p.E[2]);
-    float W[3] = {0.f, 0.f, 0.f};
-    if (MAG) {
-        W[0] = p.B[1] * m.U[2] - p.B[2] * m.U[1];
-        W[1] = p.B[2] * m.U[0] - p.B[0] * m.U[2];
-        W[2] = p.B[0] * m.U[1] - p.B[1] * m.U[0];
-    }
-    const float inv_cs = p.cs * p.inv_cs2;
-    const float om = p.omega;
-    float sum_eq = 0.f;
-    for_q<L::Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        if constexpr (q != 0) {
-            constexpr int k = shell<LAT, q>();
-            const float eu = edot<LAT, q>(m.U);
-            const float eE = edot<LAT, q>(p.E) * inv_cs;
-            const float deq = deq_moving<LAT, q>(p, m.drho, m.rho, m.j, m.U, m.U2);
-            sum_eq += deq;
-            float sig = eE * (p.A + 2.f * p.Bc * eu) + 2.f * p.C[k] * UE;
-            if (MAG) sig += 2.f * p.C[k] * edot<LAT, q>(W);
-            o[q] = d[q] + om * (deq - d[q]) + m.rho * p.what[k] * sig;
-            if (deq_out) deq_out[q] = deq;
-        }
-    });
-    const float deq0 = m.drho - sum_eq;
-    o[0] = d[0] + om * (deq0 - d[0]) + m.rho * p.what[0] * (2.f * p.C[0] * UE);
-    if (deq_out) deq_out[0] = deq0;
-}
-
-// Collision of one node (discrete BGK of Sec. 9.1 with the source of Sec. 7), then the
-// optional partial bounce-back g_q = (1 - s) d*_q + s d_qbar.
-template <int LAT, bool SOFT, bool MAG>
-__device__ __forceinline__ void collide(const Physics &p, const float *d, float s, float *o)
-{
-    using L = Lat<LAT>;
-    const Macro<LAT> m = macro<LAT>(p, d);
-    collide_bgk<LAT, MAG>(p, m, d, o);
-    if (SOFT) {
-        float t[L::Q];
-#pragma unroll
-        for (int q = 0; q < L::Q; ++q) t[q] = (1.f - s) * o[q] + s * d[L::opp[q]];
-#pragma unroll
-        for (int q = 0; q < L::Q; ++q) o[q] = t[q];
-    }
-}
-
-// ---------------------------------------------------------------------------------
-// K1: fused pull-stream + collide + force + partial bounce-back.
-// ---------------------------------------------------------------------------------
-template <int LAT, int ST, bool MASK, bool SOFT, bool MAG>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
-{
-    using L = Lat<LAT>;
-    using T = typename Codec<ST>::T;
-    const Node nd = node_of_thread(a.g, true);
-    if (nd.n < 0) return;
-    if (MASK && a.g.mask[nd.n]) return;
-    float d[L::Q], o[L::Q];
-    gather<LAT, ST, MASK>(a.g, static_cast<const T *>(a.src), a.ph.inv_scale, nd, d);
-    collide<LAT, SOFT, MAG>(a.ph, d, SOFT ? a.g.s[nd.n] : 0.f, o);
-    T *__restrict__ dst = static_cast<T *>(a.dst);
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) dst[q * a.g.stride + nd.n] = Codec<ST>::enc(o[q], a.ph.scale);
-}
-
-// ---------------------------------------------------------------------------------
-// K2: initial state. The stored state is post-collision, so node y holds, for each q,
-// the value that the next pull delivers: f^eq_q(x + e_q) when x + e_q is fluid, or
-// f^eq_qbar(x) when it is solid (bounced back).
-// ---------------------------------------------------------------------------------
 template <int LAT, int ST>
 __global__ __launch_bounds__(kBlock) void k_init(InitArgs a)
 {
     using L = Lat<LAT>;
     using T = typename Codec<ST>::T;
-    const Node nd = node_of_thread(a.g, false);
-    if (nd.n < 0) return;
-    T *__restrict__ dst = static_cast<T *>(a.dst);
     const Geometry &g = a.g;
     const Physics &p = a.ph;
+    const Tile t = tile_of<1>(g, (int)blockIdx.x, g.ntx);
+    if (!t.valid) return;
+    T *__restrict__ dst = static_cast<T *>(a.dst);
     const int N = g.nx * g.ny * g.nz;
-    if (g.mask && g.mask[nd.n]) {
+    if (g.mask && g.mask[t.own]) {
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) dst[q * g.stride + nd.n] = Codec<ST>::enc(0.f, p.scale);
+        for (int q = 0; q < L::Q; ++q) dst[q * g.stride + t.own] = Codec<ST>::enc(0.f, p.scale);
         return;
     }
-    const int xm = wrapm(nd.x, g.nx), xp = wrapp(nd.x, g.nx);
-    const int ym = wrapm(nd.y, g.ny), yp = wrapp(nd.y, g.ny);
-    const int zm = wrapm(nd.z, g.nz), zp = wrapp(nd.z, g.nz);
+    const int xm = wrapm(t.x0, g.nx), xp = wrapp(t.x0, g.nx);
+    const int ym = wrapm(t.y, g.ny), yp = wrapp(t.y, g.ny);
+    const int zm = wrapm(t.z, g.nz), zp = wrapp(t.z, g.nz);
     const float inv_cs = p.cs * p.inv_cs2;
     // rho, j, U of a node from the caller's FP64 fields (u in xi-units, j = rho c_s u)
     auto node_state = [&](int m, float &drho, float &rho, float *j, float *U, float &U2) {
@@ -290,19 +552,19 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a)
         U2 = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
     };
     float drho0, rho0, j0[3], U0[3], U20;
-    node_state(nd.n, drho0, rho0, j0, U0, U20);
+    node_state(t.own, drho0, rho0, j0, U0, U20);
     float sum_eq = 0.f;
     for_q<L::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         if constexpr (q != 0) sum_eq += deq_moving<LAT, q>(p, drho0, rho0, j0, U0, U20);
     });
-    dst[nd.n] = Codec<ST>::enc(drho0 - sum_eq, p.scale);
+    dst[t.own] = Codec<ST>::enc(drho0 - sum_eq, p.scale);
     for_q<L::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         if constexpr (q != 0) {
-            const int tx = L::ex[q] > 0 ? xp : (L::ex[q] < 0 ? xm : nd.x);
-            const int ty = L::ey[q] > 0 ? yp : (L::ey[q] < 0 ? ym : nd.y);
-            const int tz = L::ez[q] > 0 ? zp : (L::ez[q] < 0 ? zm : nd.z);
+            const int tx = L::ex[q] > 0 ? xp : (L::ex[q] < 0 ? xm : t.x0);
+            const int ty = L::ey[q] > 0 ? yp : (L::ey[q] < 0 ? ym : t.y);
+            const int tz = L::ez[q] > 0 ? zp : (L::ez[q] < 0 ? zm : t.z);
             const int tn = tx + g.nx * (ty + g.ny * tz);
             float dev;
             if (g.mask && g.mask[tn]) {
@@ -312,14 +574,13 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a)
                 node_state(tn, dr, r, j, U, U2);
                 dev = deq_moving<LAT, q>(p, dr, r, j, U, U2);
             }
-            dst[q * g.stride + nd.n] = Codec<ST>::enc(dev, p.scale);
+            dst[q * g.stride + t.own] = Codec<ST>::enc(dev, p.scale);
         }
     });
 }
 
 // ---------------------------------------------------------------------------------
-// K3/K4: gather kernels. MODE 0: rho and u fields; 1: FP64 export of the populations;
-// 2: per-block FP64 partial sums (sum drho, sum d e_x, sum d e_y, sum d e_z, nodes).
+// Block reductions.
 // ---------------------------------------------------------------------------------
 template <int NC>
 __device__ __forceinline__ void block_sum_store(double *v, double *out)
@@ -332,71 +593,33 @@ __device__ __forceinline__ void block_sum_store(double *v, double *out)
     if (lane == 0)
         for (int c = 0; c < NC; ++c) sh[wid][c] = v[c];
     __syncthreads();
-    if (threadIdx.x < NC) {
+    if ((int)threadIdx.x < NC) {
         double t = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) t += sh[w][threadIdx.x];
         out[threadIdx.x] = t;
     }
 }
 
-template <int LAT, int ST, bool MASK, int MODE>
-__global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
+// First stage of a two-stage reduction of per-block partials laid out [part][ncomp]:
+// block b sums a contiguous chunk of parts into out[b*ncomp + c] (coalesced reads).
+__global__ __launch_bounds__(kBlock) void k_reduce_stage1(const double *__restrict__ partials, int nparts,
+                                                          int ncomp, double *__restrict__ out)
 {
-    using L = Lat<LAT>;
-    using T = typename Codec<ST>::T;
-    const T *src = static_cast<const T *>(a.src);
-    if constexpr (MODE == 2) {
-        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int b = blockIdx.x; b < a.g.nblocks; b += gridDim.x) {
-            const int row = b / a.g.ntx;
-            Node nd;
-            nd.x = (b - row * a.g.ntx) * kBlock + (int)threadIdx.x;
-            nd.y = row % a.g.ny;
-            nd.z = row / a.g.ny;
-            if (nd.x >= a.g.nx) continue;
-            nd.n = nd.x + a.g.nx * row;
-            if (MASK && a.g.mask[nd.n]) continue;
-            float d[L::Q];
-            gather<LAT, ST, MASK>(a.g, src, a.ph.inv_scale, nd, d);
-            float r = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-            for (int q = 0; q < L::Q; ++q) {
-                r += d[q];
-                jx += L::ex[q] * d[q];
-                jy += L::ey[q] * d[q];
-                jz += L::ez[q] * d[q];
-            }
-            acc[0] += r;
-            acc[1] += jx;
-            acc[2] += jy;
-            acc[3] += jz;
-            acc[4] += 1.0;
-        }
-        block_sum_store<5>(acc, a.partials + (size_t)blockIdx.x * 5);
-    } else {
-        const Node nd = node_of_thread(a.g, false);
-        if (nd.n < 0) return;
-        const bool solid = MASK && a.g.mask[nd.n];
-        float d[L::Q];
-        if (!solid) gather<LAT, ST, MASK>(a.g, src, a.ph.inv_scale, nd, d);
-        if constexpr (MODE == 0) {
-            if (solid) {
-                if (a.rho) a.rho[nd.n] = 0.f;
-                if (a.u)
-                    for (int i = 0; i < L::D; ++i) a.u[(size_t)i * a.N + nd.n] = 0.f;
-                return;
-            }
-            const Macro<LAT> m = macro<LAT>(a.ph, d);
-            if (a.rho) a.rho[nd.n] = m.rho;
-            if (a.u)
-                for (int i = 0; i < L::D; ++i) a.u[(size_t)i * a.N + nd.n] = m.U[i] * a.ph.cs;
-        } else {
-            for_q<L::Q>([&](auto qc) {
-                constexpr int q = decltype(qc)::value;
-                constexpr int k = shell<LAT, q>();
-                a.f64[(size_t)q * a.N + nd.n] = solid ? 0.0 : a.what_rho0[k] + (double)d[q];
-            });
-        }
+    const int per = (nparts + gridDim.x - 1) / gridDim.x;
+    const int p0 = blockIdx.x * per;
+    const int p1 = min(nparts, p0 + per);
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = p0 * ncomp + (int)threadIdx.x; i < p1 * ncomp; i += kBlock) acc[i % ncomp] += partials[i];
+    __shared__ double sh[kBlock / 64][8];
+    for (int c = 0; c < ncomp; ++c)
+        for (int off = 32; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
+    if ((threadIdx.x & 63) == 0)
+        for (int c = 0; c < ncomp; ++c) sh[threadIdx.x >> 6][c] = acc[c];
+    __syncthreads();
+    if ((int)threadIdx.x < ncomp) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += sh[w][threadIdx.x];
+        out[(size_t)blockIdx.x * ncomp + threadIdx.x] = t;
     }
 }
 
@@ -421,6 +644,71 @@ __global__ __launch_bounds__(kBlock) void k_reduce_final(const double *__restric
 }
 
 // ---------------------------------------------------------------------------------
+// K3/K4: gather kernels over the current state. MODE 0: rho and u fields; 1: FP64
+// export of the populations; 2: per-block FP64 partial sums
+// (sum drho, sum d e_x, sum d e_y, sum d e_z, fluid nodes).
+// ---------------------------------------------------------------------------------
+template <int LAT, int ST, bool MASK, int MODE>
+__global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
+{
+    using L = Lat<LAT>;
+    using T = typename Codec<ST>::T;
+    using LT = typename LinkMask<LAT>::T;
+    const T *src = static_cast<const T *>(a.src);
+    const LT *links = static_cast<const LT *>(a.links);
+    if constexpr (MODE == 2) {
+        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int b = blockIdx.x; b < a.g.nblocks; b += gridDim.x) {
+            const Tile t = tile_of<1>(a.g, b, a.g.ntx);
+            if (!t.valid) continue;
+            LT lk[1] = {0};
+            if (MASK) {
+                lk[0] = links[t.own];
+                if (lk[0] & LinkMask<LAT>::solid) continue;
+            }
+            float d[1][L::Q];
+            gather_tile<LAT, ST, MASK, 1>(a.g, src, a.ph.inv_scale, t, lk, d);
+            const Macro<LAT> m = macro<LAT>(a.ph, d[0]);
+            acc[0] += m.drho;
+            acc[1] += m.j[0];
+            acc[2] += m.j[1];
+            if (L::D == 3) acc[3] += m.j[2];
+            acc[4] += 1.0;
+        }
+        block_sum_store<5>(acc, a.partials + (size_t)blockIdx.x * 5);
+    } else {
+        const Tile t = tile_of<1>(a.g, (int)blockIdx.x, a.g.ntx);
+        if (!t.valid) return;
+        LT lk[1] = {0};
+        bool solid = false;
+        if (MASK) {
+            lk[0] = links[t.own];
+            solid = (lk[0] & LinkMask<LAT>::solid) != 0;
+        }
+        float d[1][L::Q];
+        if (!solid) gather_tile<LAT, ST, MASK, 1>(a.g, src, a.ph.inv_scale, t, lk, d);
+        if constexpr (MODE == 0) {
+            if (solid) {
+                if (a.rho) a.rho[t.own] = 0.f;
+                if (a.u)
+                    for (int i = 0; i < L::D; ++i) a.u[(size_t)i * a.N + t.own] = 0.f;
+                return;
+            }
+            const Macro<LAT> m = macro<LAT>(a.ph, d[0]);
+            if (a.rho) a.rho[t.own] = m.rho;
+            if (a.u)
+                for (int i = 0; i < L::D; ++i) a.u[(size_t)i * a.N + t.own] = m.U[i] * a.ph.cs;
+        } else {
+            for_q<L::Q>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                constexpr int k = shell<LAT, q>();
+                a.f64[(size_t)q * a.N + t.own] = solid ? 0.0 : a.what_rho0[k] + (double)d[0][q];
+            });
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------
 // K5: one reverse step of the discrete adjoint. lam_out = dJ/df(t) from
 // lam_in = dJ/df(t+1); f(t) is pulled from the stored state as in K1.
 //   gbar_a = lam_in(x + e_a, a), or lam_in(x, abar) if x + e_a is solid;
@@ -428,7 +716,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_final(const double *__restric
 //   dJ/ds  += sum_a gbar_a (d_abar - d*_a);
 //   dJ/dtau += omega^2 sum_a hbar_a (d_a - deq_a);
 //   dJ/dE_i += sum_a hbar_a rho what_a [(A + 2 Bc e.U) e_i / c_s + 2 C_k c_s U_i];
-//   rhobar = sum_a hbar_a what_a [omega (1 + P_a) + sigma_a];
+//   rhobar = sum_a hbar_a [omega f^eq_a / rho + what_a sigma_a];
 //   V_i = sum_a hbar_a what_a [omega (A e_i + 2 Bc (e.U) e_i + 2 C_k c_s^2 U_i)
 //                              + 2 Bc e_i (e.E)/c_s + 2 C_k (c_s E_i + (e x B)_i)];
 //   lam_out_b = (1 - omega) hbar_b + s gbar_bbar + rhobar + V . (e_b / c_s^2 - U).
@@ -438,101 +726,95 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
 {
     using L = Lat<LAT>;
     using T = typename Codec<ST>::T;
+    using LT = typename LinkMask<LAT>::T;
     const Geometry &g = a.g;
     const Physics &p = a.ph;
-    const Node nd = node_of_thread(g, true);
+    const int bid = a.remap ? xcd_remap((int)blockIdx.x, g.nblocks) : (int)blockIdx.x;
+    const Tile t = tile_of<1>(g, bid, g.ntx);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (nd.n >= 0) {
-        if (MASK && g.mask[nd.n]) {
-#pragma unroll
-            for (int q = 0; q < L::Q; ++q) a.lam_out[q * g.stride + nd.n] = 0.f;
-        } else {
-            float d[L::Q], gb[L::Q];
-            gather<LAT, ST, MASK>(g, static_cast<const T *>(a.state), p.inv_scale, nd, d);
-            {
-                const int xm = wrapm(nd.x, g.nx), xp = wrapp(nd.x, g.nx);
-                const int ym = wrapm(nd.y, g.ny), yp = wrapp(nd.y, g.ny);
-                const int zm = wrapm(nd.z, g.nz), zp = wrapp(nd.z, g.nz);
-#pragma unroll
-                for (int q = 0; q < L::Q; ++q) {
-                    const int tx = L::ex[q] > 0 ? xp : (L::ex[q] < 0 ? xm : nd.x);
-                    const int ty = L::ey[q] > 0 ? yp : (L::ey[q] < 0 ? ym : nd.y);
-                    const int tz = L::ez[q] > 0 ? zp : (L::ez[q] < 0 ? zm : nd.z);
-                    const int tn = tx + g.nx * (ty + g.ny * tz);
-                    int idx = q * g.stride + tn;
-                    if (MASK && q != 0) {
-                        if (g.mask[tn]) idx = L::opp[q] * g.stride + nd.n;
-                    }
-                    gb[q] = a.lam_in[idx];
-                }
-            }
-            const float s = SOFT ? g.s[nd.n] : 0.f;
-            const Macro<LAT> m = macro<LAT>(p, d);
-            float dst[L::Q], deq[L::Q];
-            collide_bgk<LAT, MAG>(p, m, d, dst, deq);
-            const float UE = p.cs * (m.U[0] * p.E[0] + m.U[1] * p.E[1] + m.U[2] * p.E[2]);
-            float W[3] = {0.f, 0.f, 0.f};
-            if (MAG) {
-                W[0] = p.B[1] * m.U[2] - p.B[2] * m.U[1];
-                W[1] = p.B[2] * m.U[0] - p.B[0] * m.U[2];
-                W[2] = p.B[0] * m.U[1] - p.B[1] * m.U[0];
-            }
-            const float inv_cs = p.cs * p.inv_cs2;
-            const float om = p.omega;
-            const float inv_rho = 1.f / m.rho;
-            float ds = 0.f, dtau = 0.f, dE[3] = {0.f, 0.f, 0.f}, rbar = 0.f, V[3] = {0.f, 0.f, 0.f};
-            float hb[L::Q];
-            for_q<L::Q>([&](auto qc) {
-                constexpr int q = decltype(qc)::value;
-                constexpr int k = shell<LAT, q>();
-                constexpr int ex = L::ex[q], ey = L::ey[q], ez = L::ez[q];
-                const float eu = edot<LAT, q>(m.U);
-                const float eE = edot<LAT, q>(p.E) * inv_cs;
-                float sig = eE * (p.A + 2.f * p.Bc * eu) + 2.f * p.C[k] * UE;
-                if (MAG) sig += 2.f * p.C[k] * edot<LAT, q>(W);
-                const float h = (1.f - s) * gb[q];
-                hb[q] = h;
-                if (SOFT) ds += gb[q] * (d[L::opp[q]] - dst[q]);
-                dtau += h * (d[q] - deq[q]);
-                const float hw = h * p.what[k];
-                const float cE = (p.A + 2.f * p.Bc * eu) * inv_cs;
-                const float c2 = 2.f * p.C[k];
-                // dS/dE_i = rho what [cE e_i + 2 C_k c_s U_i]
-                dE[0] += hw * (cE * ex + c2 * p.cs * m.U[0]);
-                dE[1] += hw * (cE * ey + c2 * p.cs * m.U[1]);
-                dE[2] += hw * (cE * ez + c2 * p.cs * m.U[2]);
-                // Phi_q / rho = omega f^eq_q / rho + what_q sigma_q, f^eq_q = what_q rho0 + deq_q
-                rbar += h * (om * (p.what[k] * p.rho0 + deq[q]) * inv_rho) + hw * sig;
-                const float a1 = om * (p.A + 2.f * p.Bc * eu) + 2.f * p.Bc * eE;  // times e_i
-                const float a2 = om * 2.f * p.Cp[k];                                // times U_i
-                float eB[3] = {0.f, 0.f, 0.f};
-                if (MAG) {
-                    eB[0] = ey * p.B[2] - ez * p.B[1];
-                    eB[1] = ez * p.B[0] - ex * p.B[2];
-                    eB[2] = ex * p.B[1] - ey * p.B[0];
-                }
-                V[0] += hw * (a1 * ex + a2 * m.U[0] + c2 * (p.cs * p.E[0] + eB[0]));
-                V[1] += hw * (a1 * ey + a2 * m.U[1] + c2 * (p.cs * p.E[1] + eB[1]));
-                V[2] += hw * (a1 * ez + a2 * m.U[2] + c2 * (p.cs * p.E[2] + eB[2]));
-            });
-            const float VU = V[0] * m.U[0] + V[1] * m.U[1] + V[2] * m.U[2];
-            const float base = rbar - VU;
-            const float vi = p.inv_cs2;
-            for_q<L::Q>([&](auto qc) {
-                constexpr int q = decltype(qc)::value;
-                const float ev = edot<LAT, q>(V) * vi;
-                float out = (1.f - om) * hb[q] + base + ev;
-                if (SOFT) out += s * gb[L::opp[q]];
-                a.lam_out[q * g.stride + nd.n] = out;
-            });
-            if (SOFT && g.s && a.grad_s) a.grad_s[nd.n] += ds;
-            acc[0] = (double)m.rho * (double)dE[0];
-            acc[1] = (double)m.rho * (double)dE[1];
-            acc[2] = (double)m.rho * (double)dE[2];
-            acc[3] = (double)(om * om) * (double)dtau;
-        }
+    LT lk[1] = {0};
+    bool solid = false;
+    if (MASK && t.valid) {
+        lk[0] = static_cast<const LT *>(a.links)[t.own];
+        solid = (lk[0] & LinkMask<LAT>::solid) != 0;
     }
-    if (a.partials) block_sum_store<4>(acc, a.partials + (size_t)blockIdx.x * 4);
+    if (t.valid && solid) {
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) a.lam_out[q * g.stride + t.own] = 0.f;
+    } else if (t.valid) {
+        float d[1][L::Q], gb[L::Q];
+        gather_tile<LAT, ST, MASK, 1>(g, static_cast<const T *>(a.state), p.inv_scale, t, lk, d);
+        {
+            const int xm = wrapm(t.x0, g.nx), xp = wrapp(t.x0, g.nx);
+            const int ym = wrapm(t.y, g.ny), yp = wrapp(t.y, g.ny);
+            const int zm = wrapm(t.z, g.nz), zp = wrapp(t.z, g.nz);
+#pragma unroll
+            for (int q = 0; q < L::Q; ++q) {
+                const int tx = L::ex[q] > 0 ? xp : (L::ex[q] < 0 ? xm : t.x0);
+                const int ty = L::ey[q] > 0 ? yp : (L::ey[q] < 0 ? ym : t.y);
+                const int tz = L::ez[q] > 0 ? zp : (L::ez[q] < 0 ? zm : t.z);
+                int idx = q * g.stride + tx + g.nx * (ty + g.ny * tz);
+                // x + e_q solid <=> the pull of the opposite population at x bounces
+                if (MASK && q != 0 && ((lk[0] >> L::opp[q]) & 1u)) idx = L::opp[q] * g.stride + t.own;
+                gb[q] = a.lam_in[idx];
+            }
+        }
+        const float s = SOFT ? g.s[t.own] : 0.f;
+        const Macro<LAT> m = macro<LAT>(p, d[0]);
+        float dst[L::Q], deq[L::Q], sig[L::Q];
+        collide_node<LAT, MAG ? 2 : 1>(p, m, d[0], dst, deq, sig);
+        const float inv_cs = p.cs * p.inv_cs2;
+        const float om = p.omega;
+        const float inv_rho = __builtin_amdgcn_rcpf(m.rho);
+        float ds = 0.f, dtau = 0.f, dE[3] = {0.f, 0.f, 0.f}, rbar = 0.f, V[3] = {0.f, 0.f, 0.f};
+        float hb[L::Q];
+        for_q<L::Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr int k = shell<LAT, q>();
+            constexpr int ex = L::ex[q], ey = L::ey[q], ez = L::ez[q];
+            const float eu = edot<LAT, q>(m.U);
+            const float h = (1.f - s) * gb[q];
+            hb[q] = h;
+            if (SOFT) ds += gb[q] * (d[0][L::opp[q]] - dst[q]);
+            dtau += h * (d[0][q] - deq[q]);
+            const float hw = h * p.what[k];
+            const float cE = (p.A + 2.f * p.Bc * eu) * inv_cs;
+            const float c2 = p.C2[k];
+            // dS/dE_i = rho what [cE e_i + 2 C_k c_s U_i]
+            dE[0] += hw * (cE * ex + c2 * p.cs * m.U[0]);
+            dE[1] += hw * (cE * ey + c2 * p.cs * m.U[1]);
+            dE[2] += hw * (cE * ez + c2 * p.cs * m.U[2]);
+            // Phi_q / rho = omega f^eq_q / rho + what_q sigma_q, f^eq_q = what_q rho0 + deq_q
+            rbar += h * (om * (p.what[k] * p.rho0 + deq[q]) * inv_rho) + hw * sig[q];
+            const float a1 = om * (p.A + 2.f * p.Bc * eu) + p.c2q[q];  // times e_i
+            const float a2 = om * 2.f * p.Cp[k];                       // times U_i
+            float eB[3] = {0.f, 0.f, 0.f};
+            if (MAG) {
+                eB[0] = ey * p.B[2] - ez * p.B[1];
+                eB[1] = ez * p.B[0] - ex * p.B[2];
+                eB[2] = ex * p.B[1] - ey * p.B[0];
+            }
+            V[0] += hw * (a1 * ex + a2 * m.U[0] + c2 * (p.cs * p.E[0] + eB[0]));
+            V[1] += hw * (a1 * ey + a2 * m.U[1] + c2 * (p.cs * p.E[1] + eB[1]));
+            V[2] += hw * (a1 * ez + a2 * m.U[2] + c2 * (p.cs * p.E[2] + eB[2]));
+        });
+        const float VU = V[0] * m.U[0] + V[1] * m.U[1] + V[2] * m.U[2];
+        const float base = rbar - VU;
+        const float vi = p.inv_cs2;
+        for_q<L::Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const float ev = edot<LAT, q>(V) * vi;
+            float out = (1.f - om) * hb[q] + base + ev;
+            if (SOFT) out += s * gb[L::opp[q]];
+            a.lam_out[q * g.stride + t.own] = out;
+        });
+        if (SOFT && a.grad_s) a.grad_s[t.own] += ds;
+        acc[0] = (double)m.rho * (double)dE[0];
+        acc[1] = (double)m.rho * (double)dE[1];
+        acc[2] = (double)m.rho * (double)dE[2];
+        acc[3] = (double)(om * om) * (double)dtau;
+    }
+    block_sum_store<4>(acc, a.partials + (size_t)blockIdx.x * 4);
 }
 
 // Adjoint seed: lam(a, n) = e_a[axis] * value at fluid nodes (value = 1/(c_s norm)).
@@ -540,51 +822,57 @@ template <int LAT>
 __global__ __launch_bounds__(kBlock) void k_seed(Geometry g, float value, int axis, float *lam)
 {
     using L = Lat<LAT>;
-    const Node nd = node_of_thread(g, false);
-    if (nd.n < 0) return;
-    const bool solid = g.mask && g.mask[nd.n];
+    const Tile t = tile_of<1>(g, (int)blockIdx.x, g.ntx);
+    if (!t.valid) return;
+    const bool solid = g.mask && g.mask[t.own];
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
         const int e = axis == 0 ? L::ex[q] : (axis == 1 ? L::ey[q] : L::ez[q]);
-        lam[q * g.stride + nd.n] = solid ? 0.f : (float)e * value;
+        lam[q * g.stride + t.own] = solid ? 0.f : (float)e * value;
     }
 }
 
-}  // namespace
-}  // namespace lbm
 // ---------------------------------------------------------------------------------
 // Launchers: runtime flags -> template instances.
 // ---------------------------------------------------------------------------------
-namespace lbm {
-namespace {
-
-template <int LAT, int ST>
-hipError_t step_lat_st(bool mag, const StepArgs &a, hipStream_t st)
+template <int LAT, int ST, int V>
+hipError_t step_v(int force, const StepArgs &a, hipStream_t st)
 {
-    const bool mask = a.g.mask != nullptr, soft = a.g.s != nullptr;
-    const dim3 grid(a.g.nblocks), block(kBlock);
-#define LBM_STEP(M, S, B) hipLaunchKernelGGL((k_step<LAT, ST, M, S, B>), grid, block, 0, st, a)
+    const bool mask = a.links != nullptr, soft = a.g.s != nullptr;
+    const int ntx = (a.g.nx + kBlock * V - 1) / (kBlock * V);
+    const int nblocks = ntx * a.g.ny * a.g.nz;
+    const dim3 grid(nblocks), block(kBlock);
+#define LBM_STEP(M, S, F) hipLaunchKernelGGL((k_step<LAT, ST, M, S, F, V>), grid, block, 0, st, a, ntx, nblocks)
+#define LBM_STEP_F(M, S)   \
+    if (force == 0)        \
+        LBM_STEP(M, S, 0); \
+    else if (force == 1)   \
+        LBM_STEP(M, S, 1); \
+    else                   \
+        LBM_STEP(M, S, 2)
     if (mask) {
-        if (soft) {
-            if (mag) LBM_STEP(true, true, true); else LBM_STEP(true, true, false);
-        } else {
-            if (mag) LBM_STEP(true, false, true); else LBM_STEP(true, false, false);
-        }
+        if (soft) LBM_STEP_F(true, true); else LBM_STEP_F(true, false);
     } else {
-        if (soft) {
-            if (mag) LBM_STEP(false, true, true); else LBM_STEP(false, true, false);
-        } else {
-            if (mag) LBM_STEP(false, false, true); else LBM_STEP(false, false, false);
-        }
+        if (soft) LBM_STEP_F(false, true); else LBM_STEP_F(false, false);
     }
+#undef LBM_STEP_F
 #undef LBM_STEP
     return hipGetLastError();
 }
 
 template <int LAT, int ST>
+hipError_t step_lat_st(int force, const StepArgs &a, hipStream_t st)
+{
+    const int v = step_vector_width(LAT, ST, a.g.nx);
+    if (v == 4) return step_v<LAT, ST, 4>(force, a, st);
+    if (v == 2) return step_v<LAT, ST, 2>(force, a, st);
+    return step_v<LAT, ST, 1>(force, a, st);
+}
+
+template <int LAT, int ST>
 hipError_t adjoint_lat_st(bool mag, const AdjointArgs &a, hipStream_t st)
 {
-    const bool mask = a.g.mask != nullptr, soft = a.g.s != nullptr;
+    const bool mask = a.links != nullptr, soft = a.g.s != nullptr;
     const dim3 grid(a.g.nblocks), block(kBlock);
 #define LBM_ADJ(M, S, B) hipLaunchKernelGGL((k_adjoint<LAT, ST, M, S, B>), grid, block, 0, st, a)
     if (mask) {
@@ -607,7 +895,7 @@ hipError_t adjoint_lat_st(bool mag, const AdjointArgs &a, hipStream_t st)
 template <int LAT, int ST>
 hipError_t gather_lat_st(const GatherArgs &a, int nred, hipStream_t st)
 {
-    const bool mask = a.g.mask != nullptr;
+    const bool mask = a.links != nullptr;
     const dim3 block(kBlock);
     const int mode = a.partials ? 2 : (a.f64 ? 1 : 0);
     const dim3 grid(mode == 2 ? nred : a.g.nblocks);
@@ -618,6 +906,13 @@ hipError_t gather_lat_st(const GatherArgs &a, int nred, hipStream_t st)
         if (mode == 0) LBM_G(false, 0); else if (mode == 1) LBM_G(false, 1); else LBM_G(false, 2);
     }
 #undef LBM_G
+    return hipGetLastError();
+}
+
+template <int LAT, int ST>
+hipError_t init_lat_st(const InitArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_init<LAT, ST>), dim3(a.g.nblocks), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 
@@ -637,9 +932,9 @@ hipError_t gather_lat_st(const GatherArgs &a, int nred, hipStream_t st)
         return hipErrorInvalidValue;                                                      \
     } while (0)
 
-hipError_t launch_step(int lattice, int storage, bool mag, const StepArgs &a, hipStream_t st)
+hipError_t launch_step(int lattice, int storage, int force, const StepArgs &a, hipStream_t st)
 {
-    LBM_DISPATCH(step_lat_st, mag, a, st);
+    LBM_DISPATCH(step_lat_st, force, a, st);
 }
 
 hipError_t launch_adjoint(int lattice, int storage, bool mag, const AdjointArgs &a, hipStream_t st)
@@ -652,23 +947,37 @@ hipError_t launch_gather(int lattice, int storage, const GatherArgs &a, int nblo
     LBM_DISPATCH(gather_lat_st, a, nblocks_reduce, st);
 }
 
-namespace {
-template <int LAT, int ST>
-hipError_t init_lat_st(const InitArgs &a, hipStream_t st)
-{
-    hipLaunchKernelGGL((k_init<LAT, ST>), dim3(a.g.nblocks), dim3(kBlock), 0, st, a);
-    return hipGetLastError();
-}
-}  // namespace
-
 hipError_t launch_init(int lattice, int storage, const InitArgs &a, hipStream_t st)
 {
     LBM_DISPATCH(init_lat_st, a, st);
 }
 
-hipError_t launch_reduce_final(const double *partials, int nparts, int ncomp, double *out, int accumulate,
-                               hipStream_t st)
+hipError_t launch_links(int lattice, const Geometry &g, void *links, hipStream_t st)
 {
+    if (lattice == LBM_D2V9)
+        hipLaunchKernelGGL(k_links<LBM_D2V9>, dim3(g.nblocks), dim3(kBlock), 0, st, g,
+                           static_cast<LinkMask<LBM_D2V9>::T *>(links));
+    else if (lattice == LBM_D3V19)
+        hipLaunchKernelGGL(k_links<LBM_D3V19>, dim3(g.nblocks), dim3(kBlock), 0, st, g,
+                           static_cast<LinkMask<LBM_D3V19>::T *>(links));
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+size_t link_mask_bytes(int lattice) { return lattice == LBM_D2V9 ? 2 : 4; }
+
+hipError_t launch_reduce_final(const double *partials, int nparts, int ncomp, double *out, int accumulate,
+                               hipStream_t st, double *stage)
+{
+    if (ncomp > 8) return hipErrorInvalidValue;
+    if (stage && nparts > 2 * kReduceStage) {
+        hipLaunchKernelGGL(k_reduce_stage1, dim3(kReduceStage), dim3(kBlock), 0, st, partials, nparts, ncomp, stage);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        partials = stage;
+        nparts = kReduceStage;
+    }
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials, nparts, ncomp, out, accumulate);
     return hipGetLastError();
 }
