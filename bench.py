@@ -131,6 +131,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the FP32 step")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB three times with a plain device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the method runs on a "
@@ -141,6 +143,14 @@ def main():
 
     from paper_1710_09472_amd import workloads as W
     from paper_1710_09472_amd.lbm import Simulation
+
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     wl = W.throughput_2d()
     N = wl.N
