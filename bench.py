@@ -80,6 +80,35 @@ def adjoint_ratio(wl, steps: int, warmup: int):
     return t_adj, t_fwd / steps
 
 
+def adjoint_pipeline():
+    """The differentiation workload (D3V19 128^3 soft porosity, 600 steps, checkpoints every
+    50): forward run with checkpoints, then the reverse pass (segment recompute + adjoint
+    steps). Returns ms per forward step, ms per reverse step and their ratio."""
+    import torch
+    from paper_1710_09472_amd import workloads as W
+    from paper_1710_09472_amd.adjoint import Problem, adjoint_gradients, forward_with_checkpoints
+
+    wl = W.soft_porous_3d()
+    pb = Problem(wl.lattice, wl.nx, wl.ny, wl.nz, wl.steps, wl.rho, None, None, (0, 0, 0), checkpoint=50)
+    s = torch.tensor(wl.s, dtype=torch.float32, device="cuda")
+    J, sim, cps = forward_with_checkpoints(pb, wl.E, wl.tau, s)  # warm-up
+    adjoint_gradients(pb, sim, cps)
+    sim.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, sim, cps = forward_with_checkpoints(pb, wl.E, wl.tau, s)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gE, gT, gs, _ = adjoint_gradients(pb, sim, cps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    sim.close()
+    fwd, bwd = (t1 - t0) / wl.steps, (t2 - t1) / wl.steps
+    return {"workload": "soft_porous_3d: D3V19 128^3, mean s 0.2, E_x 1e-6, tau 0.75, 600 steps, K=50",
+            "forward_ms_per_step": round(fwd * 1e3, 5), "reverse_ms_per_step": round(bwd * 1e3, 5),
+            "ratio_to_forward": round(bwd / fwd, 3), "dJ_dEx": float(gE[0]), "dJ_dtau": float(gT)}
+
+
 def traffic_from_profile(kernel_tag: str):
     """HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE + WRITE_SIZE,
     scaled by a copy-kernel calibration), read from the committed summary, if the
@@ -178,8 +207,10 @@ def main():
                           "dev_scale_log2": k}
             s16.close()
         t_adj, t_fwd = adjoint_ratio(wl, max(20, args.steps // 4), 5)
-        extras["adjoint"] = {"ms_per_step": round(t_adj * 1e3, 5), "forward_ms_per_step": round(t_fwd * 1e3, 5),
-                             "ratio_to_forward": round(t_adj / t_fwd, 3)}
+        extras["adjoint"] = {"step_only_4096sq": {"ms_per_step": round(t_adj * 1e3, 5),
+                                                  "forward_ms_per_step": round(t_fwd * 1e3, 5),
+                                                  "ratio_to_forward": round(t_adj / t_fwd, 3)},
+                             "checkpointed_128cube": adjoint_pipeline()}
 
     out = {
         "metric": METRIC,
