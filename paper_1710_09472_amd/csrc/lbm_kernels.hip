@@ -233,29 +233,31 @@ __device__ __forceinline__ void gather_tile(const Geometry &g, const typename Co
     const int nx = g.nx;
     const int ym = wrapm(t.y, g.ny), yp = wrapp(t.y, g.ny);
     const int zm = wrapm(t.z, g.nz), zp = wrapp(t.z, g.nz);
-    const int xl = t.x0 == 0 ? nx - 1 : t.x0 - 1;
-    const int xr = t.x0 + V >= nx ? 0 : t.x0 + V;
+    // lane offsets are unsigned 32-bit, so loads use a scalar base and one VGPR offset
+    const unsigned x0 = (unsigned)t.x0;
+    const unsigned xl = t.x0 == 0 ? (unsigned)(nx - 1) : x0 - 1u;
+    const unsigned xr = t.x0 + V >= nx ? 0u : x0 + (unsigned)V;
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
         const int sy = L::ey[q] > 0 ? ym : (L::ey[q] < 0 ? yp : t.y);
         const int sz = L::ez[q] > 0 ? zm : (L::ez[q] < 0 ? zp : t.z);
-        const typename Codec<ST>::T *base = src + q * g.stride + nx * (sy + g.ny * sz);
+        const typename Codec<ST>::T *base = src + (size_t)q * g.stride + (size_t)nx * (sy + g.ny * sz);
         if (L::ex[q] == 0) {
             float f[V];
-            vload<ST, V>(base + t.x0, inv_scale, f);
+            vload<ST, V>(base + x0, inv_scale, f);
 #pragma unroll
             for (int i = 0; i < V; ++i) d[i][q] = f[i];
         } else if (V == 1) {
             d[0][q] = Codec<ST>::dec(base[L::ex[q] > 0 ? xl : xr], inv_scale);
         } else if (L::ex[q] > 0) {  // from x - 1
             float f[V];
-            vload<ST, V>(base + t.x0, inv_scale, f);
+            vload<ST, V>(base + x0, inv_scale, f);
             d[0][q] = Codec<ST>::dec(base[xl], inv_scale);
 #pragma unroll
             for (int i = 1; i < V; ++i) d[i][q] = f[i - 1];
         } else {  // from x + 1
             float f[V];
-            vload<ST, V>(base + t.x0, inv_scale, f);
+            vload<ST, V>(base + x0, inv_scale, f);
 #pragma unroll
             for (int i = 0; i < V - 1; ++i) d[i][q] = f[i + 1];
             d[V - 1][q] = Codec<ST>::dec(base[xr], inv_scale);
@@ -267,12 +269,13 @@ __device__ __forceinline__ void gather_tile(const Geometry &g, const typename Co
 #pragma unroll
         for (int i = 0; i < V; ++i) any |= lk[i] & (typename LinkMask<LAT>::T)~LinkMask<LAT>::solid;
         if (any) {
+            const unsigned own = (unsigned)t.own;
 #pragma unroll
             for (int i = 0; i < V; ++i) {
 #pragma unroll
                 for (int q = 1; q < L::Q; ++q)
                     if ((lk[i] >> q) & 1u)
-                        d[i][q] = Codec<ST>::dec(src[L::opp[q] * g.stride + t.own + i], inv_scale);
+                        d[i][q] = Codec<ST>::dec((src + (size_t)L::opp[q] * g.stride)[own + i], inv_scale);
             }
         }
     }
@@ -466,7 +469,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, int ntx, int nblock
     T *__restrict__ dst = static_cast<T *>(a.dst);
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-        T *p = dst + q * a.g.stride + t.own;
+        T *p = (dst + (size_t)q * a.g.stride) + (unsigned)t.own;
         if (!MASK || all_fluid) {
             float f[V];
 #pragma unroll
@@ -750,13 +753,15 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
             const int zm = wrapm(t.z, g.nz), zp = wrapp(t.z, g.nz);
 #pragma unroll
             for (int q = 0; q < L::Q; ++q) {
-                const int tx = L::ex[q] > 0 ? xp : (L::ex[q] < 0 ? xm : t.x0);
+                const unsigned tx = (unsigned)(L::ex[q] > 0 ? xp : (L::ex[q] < 0 ? xm : t.x0));
                 const int ty = L::ey[q] > 0 ? yp : (L::ey[q] < 0 ? ym : t.y);
                 const int tz = L::ez[q] > 0 ? zp : (L::ez[q] < 0 ? zm : t.z);
-                int idx = q * g.stride + tx + g.nx * (ty + g.ny * tz);
+                const float *lq = a.lam_in + (size_t)q * g.stride;
+                float v = lq[(size_t)g.nx * (ty + g.ny * tz) + tx];
                 // x + e_q solid <=> the pull of the opposite population at x bounces
-                if (MASK && q != 0 && ((lk[0] >> L::opp[q]) & 1u)) idx = L::opp[q] * g.stride + t.own;
-                gb[q] = a.lam_in[idx];
+                if (MASK && q != 0 && ((lk[0] >> L::opp[q]) & 1u))
+                    v = (a.lam_in + (size_t)L::opp[q] * g.stride)[(unsigned)t.own];
+                gb[q] = v;
             }
         }
         const float s = SOFT ? g.s[t.own] : 0.f;
@@ -766,47 +771,63 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
         const float inv_cs = p.cs * p.inv_cs2;
         const float om = p.omega;
         const float inv_rho = __builtin_amdgcn_rcpf(m.rho);
-        float ds = 0.f, dtau = 0.f, dE[3] = {0.f, 0.f, 0.f}, rbar = 0.f, V[3] = {0.f, 0.f, 0.f};
+        const float one_s = 1.f - s;
+        // Sums over q, with the q-independent factors applied once at the end:
+        //   Ee = sum hw (A + 2 Bc e.U) e,  Ve = sum hw a1 e,  Wc = sum hw 2 C_k e,
+        //   S1 = sum hw 2 C_k,  S2 = sum hw C_k c_s^2,  R1 = sum h (what rho0 + deq),
+        //   R2 = sum hw sigma, with hw = h what_k, a1 = omega (A + 2 Bc e.U) + 2 Bc (e.E)/c_s.
+        float Ee[3] = {0.f, 0.f, 0.f}, Ve[3] = {0.f, 0.f, 0.f}, Wc[3] = {0.f, 0.f, 0.f};
+        float S1 = 0.f, S2 = 0.f, R1 = 0.f, R2 = 0.f, ds = 0.f, dtau = 0.f;
         float hb[L::Q];
+        auto acc_e = [](float *acc, float v, int ex, int ey, int ez) {
+            if (ex) acc[0] += ex > 0 ? v : -v;
+            if (ey) acc[1] += ey > 0 ? v : -v;
+            if (ez) acc[2] += ez > 0 ? v : -v;
+        };
         for_q<L::Q>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             constexpr int k = shell<LAT, q>();
             constexpr int ex = L::ex[q], ey = L::ey[q], ez = L::ez[q];
-            const float eu = edot<LAT, q>(m.U);
-            const float h = (1.f - s) * gb[q];
+            const float h = one_s * gb[q];
             hb[q] = h;
-            if (SOFT) ds += gb[q] * (d[0][L::opp[q]] - dst[q]);
-            dtau += h * (d[0][q] - deq[q]);
             const float hw = h * p.what[k];
-            const float cE = (p.A + 2.f * p.Bc * eu) * inv_cs;
-            const float c2 = p.C2[k];
-            // dS/dE_i = rho what [cE e_i + 2 C_k c_s U_i]
-            dE[0] += hw * (cE * ex + c2 * p.cs * m.U[0]);
-            dE[1] += hw * (cE * ey + c2 * p.cs * m.U[1]);
-            dE[2] += hw * (cE * ez + c2 * p.cs * m.U[2]);
-            // Phi_q / rho = omega f^eq_q / rho + what_q sigma_q, f^eq_q = what_q rho0 + deq_q
-            rbar += h * (om * (p.what[k] * p.rho0 + deq[q]) * inv_rho) + hw * sig[q];
-            const float a1 = om * (p.A + 2.f * p.Bc * eu) + p.c2q[q];  // times e_i
-            const float a2 = om * 2.f * p.Cp[k];                       // times U_i
-            float eB[3] = {0.f, 0.f, 0.f};
-            if (MAG) {
-                eB[0] = ey * p.B[2] - ez * p.B[1];
-                eB[1] = ez * p.B[0] - ex * p.B[2];
-                eB[2] = ex * p.B[1] - ey * p.B[0];
+            if (SOFT) ds = __builtin_fmaf(gb[q], d[0][L::opp[q]] - dst[q], ds);
+            dtau = __builtin_fmaf(h, d[0][q] - deq[q], dtau);
+            R1 = __builtin_fmaf(h, p.what[k] * p.rho0 + deq[q], R1);
+            R2 = __builtin_fmaf(hw, sig[q], R2);
+            S1 = __builtin_fmaf(hw, p.C2[k], S1);
+            S2 = __builtin_fmaf(hw, p.Cp[k], S2);
+            if constexpr (q != 0) {
+                const float eu = edot<LAT, q>(m.U);
+                const float t1 = __builtin_fmaf(2.f * p.Bc, eu, p.A);
+                const float a1 = __builtin_fmaf(om, t1, p.c2q[q]);
+                acc_e(Ee, hw * t1, ex, ey, ez);
+                acc_e(Ve, hw * a1, ex, ey, ez);
+                if (MAG) acc_e(Wc, hw * p.C2[k], ex, ey, ez);
             }
-            V[0] += hw * (a1 * ex + a2 * m.U[0] + c2 * (p.cs * p.E[0] + eB[0]));
-            V[1] += hw * (a1 * ey + a2 * m.U[1] + c2 * (p.cs * p.E[1] + eB[1]));
-            V[2] += hw * (a1 * ez + a2 * m.U[2] + c2 * (p.cs * p.E[2] + eB[2]));
         });
+        // dJ/dE_i = sum hw [(A + 2 Bc e.U) e_i / c_s + 2 C_k c_s U_i]  (times rho below)
+        float dE[3], V[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            dE[i] = __builtin_fmaf(inv_cs, Ee[i], p.cs * m.U[i] * S1);
+            V[i] = Ve[i] + 2.f * om * S2 * m.U[i] + p.cs * p.E[i] * S1;
+        }
+        if (MAG) {  // sum hw 2 C_k (e x B) = (sum hw 2 C_k e) x B
+            V[0] += Wc[1] * p.B[2] - Wc[2] * p.B[1];
+            V[1] += Wc[2] * p.B[0] - Wc[0] * p.B[2];
+            V[2] += Wc[0] * p.B[1] - Wc[1] * p.B[0];
+        }
+        const float rbar = om * inv_rho * R1 + R2;
         const float VU = V[0] * m.U[0] + V[1] * m.U[1] + V[2] * m.U[2];
         const float base = rbar - VU;
-        const float vi = p.inv_cs2;
+        float Vs[3] = {V[0] * p.inv_cs2, V[1] * p.inv_cs2, V[2] * p.inv_cs2};
+        const float one_om = 1.f - om;
         for_q<L::Q>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            const float ev = edot<LAT, q>(V) * vi;
-            float out = (1.f - om) * hb[q] + base + ev;
-            if (SOFT) out += s * gb[L::opp[q]];
-            a.lam_out[q * g.stride + t.own] = out;
+            float out = __builtin_fmaf(one_om, hb[q], base + edot<LAT, q>(Vs));
+            if (SOFT) out = __builtin_fmaf(s, gb[L::opp[q]], out);
+            (a.lam_out + (size_t)q * g.stride)[(unsigned)t.own] = out;
         });
         if (SOFT && a.grad_s) a.grad_s[t.own] += ds;
         acc[0] = (double)m.rho * (double)dE[0];
