@@ -186,6 +186,36 @@ void fill_physics(lbm_t h)
         ph.scale = 1.0f;
         ph.inv_scale = 1.0f;
     }
+    // Forward-step constants. c0 = 1 - omega in FP32 (exact for omega >= 1/2); the linear
+    // equilibrium weights times omega are split as for lam above, with the diagonal-shell
+    // value a multiple of 2^-m for the largest m that keeps both values exact FP32 numbers
+    // and c0 + n1 ol_1 + n2 ol_2 = 1 exact, so that momentum relaxes without a bias from
+    // the rounding of the constants.
+    ph.c0 = 1.0f - ph.omega;
+    {
+        const double R = 1.0 - (double)ph.c0;
+        const double l2 = k.what[2] * k.A / (k.cs * k.cs);
+        const double n1 = 2.0, n2 = (h->D == 2) ? 4.0 : 8.0;
+        for (int m = 30; m >= 12; --m) {
+            const double sc = std::ldexp(1.0, m);
+            const double o2 = std::nearbyint(R * l2 * sc) / sc;
+            const double o1 = (R - n2 * o2) / n1;
+            if ((double)(float)o2 == o2 && (double)(float)o1 == o1 && n1 * o1 + n2 * o2 == R) {
+                ph.ol[1] = (float)o1;
+                ph.ol[2] = (float)o2;
+                break;
+            }
+        }
+    }
+    const double om = (double)ph.omega;
+    ph.omBc = (float)(om * k.Bc);
+    for (int s = 0; s < 4; ++s) {
+        ph.owhat[s] = (float)(om * k.what[s]);
+        ph.whatS[s] = (float)(k.what[s] * (double)ph.scale);
+        ph.oCp[s] = (float)(om * k.C[s] * k.cs * k.cs);
+    }
+    for (int i = 0; i < 3; ++i) ph.c1v[i] = (float)(k.A * h->p.E[i] / k.cs);
+    ph.inv_cs2S = (float)(1.0 / (k.cs * k.cs) / (double)ph.scale);
 }
 
 bool has_B(const lbm_t h) { return h->p.B[0] != 0.0 || h->p.B[1] != 0.0 || h->p.B[2] != 0.0; }

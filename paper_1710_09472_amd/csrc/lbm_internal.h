@@ -67,6 +67,17 @@ struct Physics {
     float c1q[kQMax]; // A (e_q.E) / c_s, library velocity order
     float c2q[kQMax]; // 2 Bc (e_q.E) / c_s
     float scale, inv_scale;  // storage scale (F16: 2^k), 1 otherwise
+    // Forward step in stored units (deviations x scale), omega folded per shell:
+    // o_q = c0 D_q + ol_k e_q.j + owhat_k drho + whatS_k rho [omega (Bc (e_q.U)^2 + Cp_k U^2)
+    //       + source_q], and o_0 from mass closure.
+    float c0;         // 1 - omega
+    float ol[4];      // ~omega lam_k, with c0 + n1 ol_1 + n2 ol_2 = 1 exactly
+    float owhat[4];   // omega what_k
+    float whatS[4];   // what_k scale
+    float omBc;       // omega Bc
+    float oCp[4];     // omega Cp_k
+    float c1v[3];     // A E / c_s, so that c1q = e_q . c1v
+    float inv_cs2S;   // inv_cs2 / scale
 };
 
 struct StepArgs {

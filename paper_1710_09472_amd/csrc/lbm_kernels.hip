@@ -18,6 +18,7 @@
 #include "lbm_internal.h"
 
 #include <cstdlib>
+#include <type_traits>
 
 #ifndef LBM_NT_STORE
 #define LBM_NT_STORE 1
@@ -125,6 +126,16 @@ __device__ __forceinline__ void vstore(typename Codec<ST>::T *p, float scale, co
         *reinterpret_cast<VT *>(p) = v;
 #endif
     }
+}
+
+// base + idx elements with the byte offset formed in 32 bits, so that a load or store
+// takes the uniform base in SGPRs and one VGPR offset instead of a 64-bit lane address.
+// Every array indexed this way is below 4 GiB (Q * stride < 2^31 elements).
+template <class T>
+__device__ __forceinline__ T *at32(T *base, unsigned idx)
+{
+    using C = std::conditional_t<std::is_const_v<T>, const char, char>;
+    return reinterpret_cast<T *>(reinterpret_cast<C *>(base) + idx * (unsigned)sizeof(T));
 }
 
 // ---------------------------------------------------------------------------------
@@ -244,23 +255,23 @@ __device__ __forceinline__ void gather_tile(const Geometry &g, const typename Co
         const typename Codec<ST>::T *base = src + (size_t)q * g.stride + (size_t)nx * (sy + g.ny * sz);
         if (L::ex[q] == 0) {
             float f[V];
-            vload<ST, V>(base + x0, inv_scale, f);
+            vload<ST, V>(at32(base, x0), inv_scale, f);
 #pragma unroll
             for (int i = 0; i < V; ++i) d[i][q] = f[i];
         } else if (V == 1) {
-            d[0][q] = Codec<ST>::dec(base[L::ex[q] > 0 ? xl : xr], inv_scale);
+            d[0][q] = Codec<ST>::dec(*at32(base, L::ex[q] > 0 ? xl : xr), inv_scale);
         } else if (L::ex[q] > 0) {  // from x - 1
             float f[V];
-            vload<ST, V>(base + x0, inv_scale, f);
-            d[0][q] = Codec<ST>::dec(base[xl], inv_scale);
+            vload<ST, V>(at32(base, x0), inv_scale, f);
+            d[0][q] = Codec<ST>::dec(*at32(base, xl), inv_scale);
 #pragma unroll
             for (int i = 1; i < V; ++i) d[i][q] = f[i - 1];
         } else {  // from x + 1
             float f[V];
-            vload<ST, V>(base + x0, inv_scale, f);
+            vload<ST, V>(at32(base, x0), inv_scale, f);
 #pragma unroll
             for (int i = 0; i < V - 1; ++i) d[i][q] = f[i + 1];
-            d[V - 1][q] = Codec<ST>::dec(base[xr], inv_scale);
+            d[V - 1][q] = Codec<ST>::dec(*at32(base, xr), inv_scale);
         }
     }
     if (MASK) {
@@ -275,7 +286,7 @@ __device__ __forceinline__ void gather_tile(const Geometry &g, const typename Co
 #pragma unroll
                 for (int q = 1; q < L::Q; ++q)
                     if ((lk[i] >> q) & 1u)
-                        d[i][q] = Codec<ST>::dec((src + (size_t)L::opp[q] * g.stride)[own + i], inv_scale);
+                        d[i][q] = Codec<ST>::dec(*at32(src + (size_t)L::opp[q] * g.stride, own + i), inv_scale);
             }
         }
     }
@@ -287,10 +298,10 @@ __device__ __forceinline__ void load_links(const typename LinkMask<LAT>::T *link
 {
     using LT = typename LinkMask<LAT>::T;
     if constexpr (V == 1) {
-        lk[0] = links[own];
+        lk[0] = *at32(links, (unsigned)own);
     } else {
         typedef LT VT __attribute__((ext_vector_type(V)));
-        const VT v = *reinterpret_cast<const VT *>(links + own);
+        const VT v = *reinterpret_cast<const VT *>(at32(links, (unsigned)own));
 #pragma unroll
         for (int i = 0; i < V; ++i) lk[i] = v[i];
     }
@@ -315,15 +326,15 @@ struct Macro {
     float drho, rho, j[3], U[3], U2;
 };
 
+// Zeroth and first moments of the deviations: r = sum_q d_q, j = sum_q d_q e_q.
 template <int LAT>
-__device__ __forceinline__ Macro<LAT> macro(const Physics &p, const float *d)
+__device__ __forceinline__ void moment_sums(const float *d, float &r, float (&j)[3])
 {
     using L = Lat<LAT>;
-    Macro<LAT> m;
-    float r = d[0];
+    r = d[0];
 #pragma unroll
     for (int q = 1; q < L::Q; ++q) r += d[q];
-    float j[3] = {0.f, 0.f, 0.f};
+    j[0] = j[1] = j[2] = 0.f;
     bool fx = true, fy = true, fz = true;
 #pragma unroll
     for (int q = 1; q < L::Q; ++q) {
@@ -343,6 +354,15 @@ __device__ __forceinline__ Macro<LAT> macro(const Physics &p, const float *d)
             fz = false;
         }
     }
+}
+
+template <int LAT>
+__device__ __forceinline__ Macro<LAT> macro(const Physics &p, const float *d)
+{
+    using L = Lat<LAT>;
+    Macro<LAT> m;
+    float r, j[3];
+    moment_sums<LAT>(d, r, j);
     m.drho = r;
     m.rho = p.rho0 + r;
     const float k = p.inv_cs2 * __builtin_amdgcn_rcpf(m.rho);
@@ -418,16 +438,81 @@ __device__ __forceinline__ void collide_node(const Physics &p, const Macro<LAT> 
     if (deq_out) deq_out[0] = deq0;
 }
 
-template <int LAT, bool SOFT, int FORCE>
-__device__ __forceinline__ void collide(const Physics &p, const float *d, float s, float *o)
+// Forward collision of one node in stored units (deviations times the storage scale S):
+// BGK relaxation toward the reduced equilibrium plus the Lorentz source, with omega and S
+// folded into per-shell constants,
+//   o_q = (1 - omega) D_q + omega S deq_q + S w_q rho sigma_q
+//       = c0 D_q + ol_k (e_q.j) + owhat_k drho + whatS_k rho [omega Bc (e_q.U)^2
+//         + omega Cp_k U^2 + sigma_q],
+// sigma_q = (e_q.c1v) + c2q (e_q.U) + C2_k c_s (U.E) + C2_k e_q.(U x B). The rest population
+// follows from mass closure (relaxation and source conserve mass), o_0 = sum_q D_q -
+// sum_{q>0} o_q, which also keeps FP32 mass conservation exact up to one rounding per node.
+template <int LAT, int FORCE>
+__device__ __forceinline__ void relax_node(const Physics &p, const float *D, float *o)
 {
     using L = Lat<LAT>;
-    const Macro<LAT> m = macro<LAT>(p, d);
-    collide_node<LAT, FORCE>(p, m, d, o);
+    float drho, j[3];  // stored units
+    moment_sums<LAT>(D, drho, j);
+    const float rho = __builtin_fmaf(drho, p.inv_scale, p.rho0);
+    const float kk = p.inv_cs2S * __builtin_amdgcn_rcpf(rho);
+    float U[3] = {j[0] * kk, j[1] * kk, L::D == 3 ? j[2] * kk : 0.f};
+    float U2 = U[0] * U[0] + U[1] * U[1];
+    if constexpr (L::D == 3) U2 = __builtin_fmaf(U[2], U[2], U2);
+    float wr[3], owd[3], P[3];
+#pragma unroll
+    for (int k = 1; k < 3; ++k) {
+        wr[k] = p.whatS[k] * rho;
+        owd[k] = p.owhat[k] * drho;
+        P[k] = p.oCp[k] * U2;
+    }
+    float H[3][3];
+    if constexpr (FORCE >= 1) {
+        float UE = U[0] * p.E[0] + U[1] * p.E[1];
+        if constexpr (L::D == 3) UE = __builtin_fmaf(U[2], p.E[2], UE);
+        UE *= p.cs;
+#pragma unroll
+        for (int k = 1; k < 3; ++k) P[k] = __builtin_fmaf(p.C2[k], UE, P[k]);
+    }
+    if constexpr (FORCE == 2) {
+        const float W[3] = {p.B[1] * U[2] - p.B[2] * U[1], p.B[2] * U[0] - p.B[0] * U[2],
+                            p.B[0] * U[1] - p.B[1] * U[0]};
+#pragma unroll
+        for (int k = 1; k < 3; ++k)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) H[k][i] = __builtin_fmaf(p.C2[k], W[i], p.c1v[i]);
+    }
+    float sum = 0.f;
+    for_q<L::Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        if constexpr (q != 0) {
+            constexpr int k = shell<LAT, q>();
+            const float eu = edot<LAT, q>(U);
+            const float ej = edot<LAT, q>(j);
+            float inner;
+            if constexpr (FORCE == 0)
+                inner = __builtin_fmaf(p.omBc * eu, eu, P[k]);
+            else if constexpr (FORCE == 1)
+                inner = __builtin_fmaf(__builtin_fmaf(p.omBc, eu, p.c2q[q]), eu, P[k] + p.c1q[q]);
+            else
+                inner = __builtin_fmaf(__builtin_fmaf(p.omBc, eu, p.c2q[q]), eu, P[k] + edot<LAT, q>(H[k]));
+            const float v = __builtin_fmaf(wr[k], inner,
+                                           __builtin_fmaf(p.ol[k], ej, __builtin_fmaf(p.c0, D[q], owd[k])));
+            o[q] = v;
+            sum = (q == 1) ? v : sum + v;
+        }
+    });
+    o[0] = drho - sum;
+}
+
+template <int LAT, bool SOFT, int FORCE>
+__device__ __forceinline__ void collide(const Physics &p, const float *D, float s, float *o)
+{
+    using L = Lat<LAT>;
+    relax_node<LAT, FORCE>(p, D, o);
     if (SOFT) {
         float t[L::Q];
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) t[q] = __builtin_fmaf(s, d[L::opp[q]] - o[q], o[q]);
+        for (int q = 0; q < L::Q; ++q) t[q] = __builtin_fmaf(s, D[L::opp[q]] - o[q], o[q]);
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) o[q] = t[q];
     }
@@ -459,9 +544,10 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, int ntx, int nblock
         if (!any_fluid) return;
     }
     float d[V][L::Q];
-    gather_tile<LAT, ST, MASK, V>(a.g, static_cast<const T *>(a.src), a.ph.inv_scale, t, lk, d);
+    // stored units throughout: no decode or encode scaling
+    gather_tile<LAT, ST, MASK, V>(a.g, static_cast<const T *>(a.src), 1.f, t, lk, d);
     float sv[V];
-    if (SOFT) vload<LBM_F32, V>(a.g.s + t.own, 1.f, sv);
+    if (SOFT) vload<LBM_F32, V>(at32(a.g.s, (unsigned)t.own), 1.f, sv);
     float o[V][L::Q];
 #pragma unroll
     for (int i = 0; i < V; ++i) collide<LAT, SOFT, FORCE>(a.ph, d[i], SOFT ? sv[i] : 0.f, o[i]);
@@ -469,16 +555,16 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, int ntx, int nblock
     T *__restrict__ dst = static_cast<T *>(a.dst);
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-        T *p = (dst + (size_t)q * a.g.stride) + (unsigned)t.own;
+        T *p = at32(dst + (size_t)q * a.g.stride, (unsigned)t.own);
         if (!MASK || all_fluid) {
             float f[V];
 #pragma unroll
             for (int i = 0; i < V; ++i) f[i] = o[i][q];
-            vstore<ST, V>(p, a.ph.scale, f);
+            vstore<ST, V>(p, 1.f, f);
         } else {
 #pragma unroll
             for (int i = 0; i < V; ++i)
-                if (fluid[i]) p[i] = Codec<ST>::enc(o[i][q], a.ph.scale);
+                if (fluid[i]) *at32(p, (unsigned)i) = Codec<ST>::enc(o[i][q], 1.f);
         }
     }
 }
@@ -738,12 +824,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
     LT lk[1] = {0};
     bool solid = false;
     if (MASK && t.valid) {
-        lk[0] = static_cast<const LT *>(a.links)[t.own];
+        lk[0] = *at32(static_cast<const LT *>(a.links), (unsigned)t.own);
         solid = (lk[0] & LinkMask<LAT>::solid) != 0;
     }
     if (t.valid && solid) {
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) a.lam_out[q * g.stride + t.own] = 0.f;
+        for (int q = 0; q < L::Q; ++q) *at32(a.lam_out + (size_t)q * g.stride, (unsigned)t.own) = 0.f;
     } else if (t.valid) {
         float d[1][L::Q], gb[L::Q];
         gather_tile<LAT, ST, MASK, 1>(g, static_cast<const T *>(a.state), p.inv_scale, t, lk, d);
@@ -757,14 +843,14 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
                 const int ty = L::ey[q] > 0 ? yp : (L::ey[q] < 0 ? ym : t.y);
                 const int tz = L::ez[q] > 0 ? zp : (L::ez[q] < 0 ? zm : t.z);
                 const float *lq = a.lam_in + (size_t)q * g.stride;
-                float v = lq[(size_t)g.nx * (ty + g.ny * tz) + tx];
+                float v = *at32(lq + (size_t)g.nx * (ty + g.ny * tz), tx);
                 // x + e_q solid <=> the pull of the opposite population at x bounces
                 if (MASK && q != 0 && ((lk[0] >> L::opp[q]) & 1u))
-                    v = (a.lam_in + (size_t)L::opp[q] * g.stride)[(unsigned)t.own];
+                    v = *at32(a.lam_in + (size_t)L::opp[q] * g.stride, (unsigned)t.own);
                 gb[q] = v;
             }
         }
-        const float s = SOFT ? g.s[t.own] : 0.f;
+        const float s = SOFT ? *at32(g.s, (unsigned)t.own) : 0.f;
         const Macro<LAT> m = macro<LAT>(p, d[0]);
         float dst[L::Q], deq[L::Q], sig[L::Q];
         collide_node<LAT, MAG ? 2 : 1>(p, m, d[0], dst, deq, sig);
@@ -827,7 +913,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
             constexpr int q = decltype(qc)::value;
             float out = __builtin_fmaf(one_om, hb[q], base + edot<LAT, q>(Vs));
             if (SOFT) out = __builtin_fmaf(s, gb[L::opp[q]], out);
-            (a.lam_out + (size_t)q * g.stride)[(unsigned)t.own] = out;
+            *at32(a.lam_out + (size_t)q * g.stride, (unsigned)t.own) = out;
         });
         if (SOFT && a.grad_s) a.grad_s[t.own] += ds;
         acc[0] = (double)m.rho * (double)dE[0];
