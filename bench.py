@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the semiclassical LBM step on one MI355X.
 
-Workload: the 4096 x 4096 fully periodic D2V9 grid with the Fermi-Dirac electron
+Default workload: the 4096 x 4096 fully periodic D2V9 grid with the Fermi-Dirac electron
 weight (theta = 1/270, mu = 1), rho = 1 + 0.01 N(0,1) (seed 1), u = 0, tau = 0.6.
 A timed step is one fused collide-and-stream update of every node (pull streaming,
 moments, equilibrium, Lorentz source, BGK relaxation, store) in FP32 arithmetic with
@@ -12,7 +12,12 @@ Prints one JSON line: MLUPS (value), ms per step, the roofline of the step kerne
 the FP16- and BF16-storage steps, the adjoint step relative to the forward step, and
 the FP64 CPU oracle timed on this host on a bounded sample of the same workload.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+--workload selects one of the other full-size workloads (the 256x128x128 D3V19 Hall
+duct, the 2048^2 D2V9 disk packing, the 128^3 D3V19 soft-porosity box) and --storage
+its storage format; those runs time the step alone (no FP16/BF16 or adjoint extras).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                       [--storage f32|f16|bf16] [--no-cpu-baseline] [--no-extras]
 """
 from __future__ import annotations
 
@@ -32,9 +37,45 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_DIR = ROOT / "profiles"
 
 
+# dev_scale_log2 of the FP16 runs: max|deviation| x 2^k near 2^12 for each workload
+F16_SCALE = {"throughput_2d": 12, "hall_duct_3d": 28, "porous_ohm_2d": 25, "soft_porous_3d": 28}
+
+
+WORKLOAD_DESC = {
+    "throughput_2d": "throughput_2d: D2V9 4096x4096 periodic, Fermi-Dirac weight theta=1/270 mu=1, "
+                     "rho=1+0.01N(0,1) seed 1, u=0, tau=0.6",
+    "hall_duct_3d": "hall_duct_3d: D3V19 256x128x128, solid planes y,z in {0,127}, periodic x, "
+                    "E=(1e-6,0,0), B=(0,0,1e-3), tau=0.7",
+    "porous_ohm_2d": "porous_ohm_2d: D2V9 2048x2048 periodic, radius-8 disks to solid fraction 0.30 (seed 2), "
+                     "E_x=1e-7, tau=0.9",
+    "soft_porous_3d": "soft_porous_3d: D3V19 128^3 periodic, partial bounce-back field s of mean 0.2 (seed 3), "
+                      "E_x=1e-6, tau=0.75",
+}
+
+
+def make_workload(name: str):
+    from paper_1710_09472_amd import workloads as W
+
+    return {"throughput_2d": W.throughput_2d, "hall_duct_3d": W.hall_duct_3d,
+            "porous_ohm_2d": W.porous_ohm_2d, "soft_porous_3d": W.soft_porous_3d}[name]()
+
+
 def bytes_per_node(Q: int, elem: int) -> int:
     """Algorithmic HBM bytes of one node update: Q populations read and Q written."""
     return 2 * Q * elem
+
+
+def algorithmic_bytes(wl, Q: int, elem: int) -> int:
+    """Minimum HBM bytes of one step: the populations of every fluid node read and
+    written once, plus one byte of solid flag per node where there are solids and the
+    FP32 porosity field where there is one."""
+    fluid = wl.N if wl.mask is None else int((wl.mask == 0).sum())
+    b = fluid * bytes_per_node(Q, elem)
+    if wl.mask is not None:
+        b += wl.N
+    if wl.s is not None:
+        b += 4 * wl.N
+    return b
 
 
 def timed_steps(sim, steps: int, warmup: int):
@@ -130,28 +171,34 @@ def traffic_from_profile(kernel_tag: str):
 
 
 def cpu_baseline(wl, target_s: float = 12.0):
-    """The FP64 oracle on this host's cores, on a 4096 x 256 strip of the same grid
-    (same rho field rows, periodic), scaled to MLUPS."""
+    """The FP64 oracle on this host's cores on a slab of the same workload (the first
+    256 rows of a 2D grid, the first planes of a 3D grid, about half a million nodes,
+    periodic, with the same solids and porosity), scaled to MLUPS."""
     import numpy as np
 
     from oracle.oracle import OracleModel, get_threads
 
-    ny = 256
-    sub_rho = wl.rho.reshape(wl.ny, wl.nx)[:ny].reshape(-1)
-    m = OracleModel("D2V9", wl.nx, ny, 1, tau=wl.tau)
-    f = m.init_state(sub_rho)
-    f = m.run(f, 1)  # first call: thread start-up and page faults, not timed
+    nz = 1 if wl.nz == 1 else max(2, (1 << 19) // (wl.nx * wl.ny))
+    ny = min(wl.ny, 256) if wl.nz == 1 else wl.ny
+    n = wl.nx * ny * nz
+    cut = lambda a: None if a is None else a.reshape(wl.nz, wl.ny, wl.nx)[:nz, :ny].reshape(-1)
+    m = OracleModel(wl.lattice, wl.nx, ny, nz, tau=wl.tau, E=wl.E, B=wl.B)
+    mask, s = cut(wl.mask), cut(wl.s)
+    f = m.init_state(cut(wl.rho), mask=mask)
+    f = m.run(f, 1, mask=mask, s=s)  # first call: thread start-up and page faults, not timed
     t0 = time.perf_counter()
-    f = m.run(f, 5)
+    f = m.run(f, 5, mask=mask, s=s)
     one = (time.perf_counter() - t0) / 5
     steps = max(1, int(target_s / max(one, 1e-4)))
     t0 = time.perf_counter()
-    f = m.run(f, steps)
+    f = m.run(f, steps, mask=mask, s=s)
     dt = time.perf_counter() - t0
     assert np.isfinite(f).all()
-    mlups = wl.nx * ny * steps / dt / 1e6
+    mlups = n * steps / dt / 1e6
+    dims = f"{wl.nx}x{ny}" + (f"x{nz}" if wl.nz > 1 else "")
+    full = f"{wl.nx}x{wl.ny}" + (f"x{wl.nz}" if wl.nz > 1 else "")
     return {"value": round(mlups, 3), "unit": "MLUPS", "cores": get_threads(), "kind": "oracle",
-            "sample": f"D2V9 {wl.nx}x{ny} strip of the 4096x4096 grid, FP64, {steps} steps in {dt:.1f} s"}
+            "sample": f"{wl.lattice} {dims} slab of the {full} grid, FP64, {steps} steps in {dt:.1f} s"}
 
 
 def main():
@@ -159,8 +206,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="throughput_2d", choices=sorted(WORKLOAD_DESC))
+    ap.add_argument("--storage", default="f32", choices=("f32", "f16", "bf16"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="only the FP32 step")
+    ap.add_argument("--no-extras", action="store_true", help="only the main step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB three times with a plain device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -171,7 +220,6 @@ def main():
 
     import torch
 
-    from paper_1710_09472_amd import workloads as W
     from paper_1710_09472_amd.lbm import Simulation
 
     if args.copy_calibration:
@@ -182,30 +230,37 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    wl = W.throughput_2d()
+    wl = make_workload(args.workload)
     N = wl.N
-    sim = Simulation(wl.lattice, wl.nx, wl.ny, 1, tau=wl.tau)
-    sim.init(wl.rho)
+    st = args.storage
+    elem = 4 if st == "f32" else 2
+    k16 = F16_SCALE[args.workload] if st == "f16" else 0
+    sim = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E, B=wl.B, storage=st,
+                     dev_scale_log2=k16, mask=wl.mask, s=wl.s)
+    sim.init(wl.rho, wl.u)
     wall, ev = timed_steps(sim, args.steps, args.warmup)
     t_launch = ev / args.steps
     mlups = N * args.steps / wall / 1e6
-    alg = bytes_per_node(sim.Q, 4) * N
+    alg = algorithmic_bytes(wl, sim.Q, elem)
     achieved = alg / t_launch / 1e9
-    traffic = traffic_from_profile("k_step_D2V9_f32_4096x4096")
+    dims = f"{wl.nx}x{wl.ny}" + (f"x{wl.nz}" if wl.nz > 1 else "")
+    traffic = traffic_from_profile(f"k_step_{wl.lattice}_{st}_{dims}")
     tot = sim.current()
     sim.close()
     del sim
 
+    default = args.workload == "throughput_2d" and st == "f32"
     extras = {}
-    if not args.no_extras:
-        for st, k in (("f16", 12), ("bf16", 0)):
-            s16 = Simulation(wl.lattice, wl.nx, wl.ny, 1, tau=wl.tau, storage=st, dev_scale_log2=k)
+    if default and not args.no_extras:
+        for s16s, k in (("f16", F16_SCALE["throughput_2d"]), ("bf16", 0)):
+            s16 = Simulation(wl.lattice, wl.nx, wl.ny, 1, tau=wl.tau, storage=s16s, dev_scale_log2=k)
             s16.init(wl.rho)
             w16, e16 = timed_steps(s16, args.steps, args.warmup)
             t16 = e16 / args.steps
-            extras[st] = {"MLUPS": round(N * args.steps / w16 / 1e6, 1), "ms_per_step": round(w16 / args.steps * 1e3, 5),
-                          "achieved_GBs": round(bytes_per_node(s16.Q, 2) * N / t16 / 1e9, 1),
-                          "dev_scale_log2": k}
+            extras[s16s] = {"MLUPS": round(N * args.steps / w16 / 1e6, 1),
+                            "ms_per_step": round(w16 / args.steps * 1e3, 5),
+                            "achieved_GBs": round(bytes_per_node(s16.Q, 2) * N / t16 / 1e9, 1),
+                            "dev_scale_log2": k}
             s16.close()
         t_adj, t_fwd = adjoint_ratio(wl, max(20, args.steps // 4), 5)
         extras["adjoint"] = {"step_only_4096sq": {"ms_per_step": round(t_adj * 1e3, 5),
@@ -213,6 +268,10 @@ def main():
                                                   "ratio_to_forward": round(t_adj / t_fwd, 3)},
                              "checkpointed_128cube": adjoint_pipeline()}
 
+    kernel = f"k_step<{wl.lattice},{st.upper()}" + (",mask" if wl.mask is not None else "") + \
+        (",soft" if wl.s is not None else "") + ">"
+    desc = WORKLOAD_DESC[args.workload] + {"f32": ", FP32", "f16": f", FP16 x 2^{k16}", "bf16": ", BF16"}[st] + \
+        " deviation storage"
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -226,17 +285,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "throughput_2d: D2V9 4096x4096 periodic, Fermi-Dirac weight theta=1/270 mu=1, "
-                               "rho=1+0.01N(0,1) seed 1, u=0, tau=0.6, FP32 deviation storage",
-                   "lattice": "D2V9", "nx": wl.nx, "ny": wl.ny, "storage": "f32"},
+        "config": {"workload": desc, "lattice": wl.lattice, "nx": wl.nx, "ny": wl.ny, "nz": wl.nz, "storage": st},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_step<D2V9,F32>", "bytes_per_launch": alg,
+                     "kernel": kernel, "bytes_per_launch": alg,
                      "avg_launch_ms": round(t_launch * 1e3, 5)},
-        "storage16": extras.get("f16") and {"f16": extras["f16"], "bf16": extras["bf16"]},
-        "adjoint": extras.get("adjoint"),
-        "mass_after_run": tot[0],
     }
+    if wl.mask is not None:
+        out["fluid_MLUPS"] = round(int((wl.mask == 0).sum()) * args.steps / wall / 1e6, 1)
+    if default:
+        out["storage16"] = extras.get("f16") and {"f16": extras["f16"], "bf16": extras["bf16"]}
+        out["adjoint"] = extras.get("adjoint")
+    out["mass_after_run"] = tot[0]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

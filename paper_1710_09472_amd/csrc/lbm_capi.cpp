@@ -345,6 +345,8 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *s
     h->g.stride = sz.stride;
     h->g.ntx = sz.ntx;
     h->g.nblocks = sz.nblocks;
+    h->g.div_ntx = make_fastdiv(sz.ntx);
+    h->g.div_ny = make_fastdiv(p->ny);
     h->g.mask = mask;
     h->g.s = s;
     fill_physics(h);

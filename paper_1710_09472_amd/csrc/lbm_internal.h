@@ -40,11 +40,28 @@ struct Lat<LBM_D3V19> {
 // Kernel argument block (passed by value). Float constants are the FP64 host constants
 // rounded once to FP32.
 // ---------------------------------------------------------------------------------
+// n / d for 0 <= n < 2^31 as (n m) >> sh, with l = ceil(log2 d), m = ceil(2^(31+l) / d)
+// and sh = 31 + l: m < 2^32, and the excess n (m d - 2^(31+l)) / (d 2^(31+l)) < 1/d never
+// carries n / d past the next integer.
+struct FastDiv {
+    uint32_t m;
+    uint32_t sh;
+};
+
+inline FastDiv make_fastdiv(int d)
+{
+    uint32_t l = 0;
+    while ((1ll << l) < (long long)d) ++l;
+    return FastDiv{(uint32_t)(((1ull << (31 + l)) + (uint64_t)d - 1) / (uint64_t)d), 31 + l};
+}
+
 struct Geometry {
     int nx, ny, nz;
     int stride;       // elements between population arrays
     int ntx;          // 256-node tiles per x row
     int nblocks;      // tiles in the grid = ntx * ny * nz
+    FastDiv div_ntx;  // division by ntx
+    FastDiv div_ny;   // division by ny
     const uint8_t *mask;  // nullable
     const float *s;       // nullable
 };

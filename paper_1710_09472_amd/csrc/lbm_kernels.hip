@@ -219,20 +219,28 @@ struct Tile {
     bool valid;    // the thread owns nodes
 };
 
-template <int V>
-__device__ __forceinline__ Tile tile_of(const Geometry &g, int bid, int ntx)
+__device__ __forceinline__ int fast_div(int n, FastDiv f)
 {
-    const int row = bid / ntx;
+    return (int)(((uint64_t)(uint32_t)n * f.m) >> f.sh);
+}
+
+// Block bid covers kBlock * V nodes of one x row; ntx such blocks per row.
+template <int V>
+__device__ __forceinline__ Tile tile_of(const Geometry &g, int bid, int ntx, FastDiv div_ntx)
+{
+    const int row = fast_div(bid, div_ntx);
     Tile t;
     int x0 = ((bid - row * ntx) * kBlock + (int)threadIdx.x) * V;
     t.valid = x0 < g.nx;
     if (!t.valid) x0 = g.nx - V;
     t.x0 = x0;
-    t.y = row % g.ny;
-    t.z = row / g.ny;
+    t.z = fast_div(row, g.div_ny);
+    t.y = row - t.z * g.ny;
     t.own = x0 + g.nx * row;
     return t;
 }
+
+__device__ __forceinline__ Tile tile_of(const Geometry &g, int bid) { return tile_of<1>(g, bid, g.ntx, g.div_ntx); }
 
 // Pull the pre-collision deviations of the V nodes of tile t; lk holds their link masks.
 template <int LAT, int ST, bool MASK, int V>
@@ -522,13 +530,13 @@ __device__ __forceinline__ void collide(const Physics &p, const float *D, float 
 // K1: fused pull-stream + collide + force + partial bounce-back.
 // ---------------------------------------------------------------------------------
 template <int LAT, int ST, bool MASK, bool SOFT, int FORCE, int V>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs a, int ntx, int nblocks)
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs a, int ntx, FastDiv div_ntx, int nblocks)
 {
     using L = Lat<LAT>;
     using T = typename Codec<ST>::T;
     using LT = typename LinkMask<LAT>::T;
     const int bid = a.remap ? xcd_remap((int)blockIdx.x, nblocks) : (int)blockIdx.x;
-    const Tile t = tile_of<V>(a.g, bid, ntx);
+    const Tile t = tile_of<V>(a.g, bid, ntx, div_ntx);
     LT lk[V];
     bool fluid[V];
     bool all_fluid = true;
@@ -577,7 +585,7 @@ __global__ __launch_bounds__(kBlock) void k_links(Geometry g, typename LinkMask<
 {
     using L = Lat<LAT>;
     using LT = typename LinkMask<LAT>::T;
-    const Tile t = tile_of<1>(g, (int)blockIdx.x, g.ntx);
+    const Tile t = tile_of(g, (int)blockIdx.x);
     if (!t.valid) return;
     const int xm = wrapm(t.x0, g.nx), xp = wrapp(t.x0, g.nx);
     const int ym = wrapm(t.y, g.ny), yp = wrapp(t.y, g.ny);
@@ -615,7 +623,7 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a)
     using T = typename Codec<ST>::T;
     const Geometry &g = a.g;
     const Physics &p = a.ph;
-    const Tile t = tile_of<1>(g, (int)blockIdx.x, g.ntx);
+    const Tile t = tile_of(g, (int)blockIdx.x);
     if (!t.valid) return;
     T *__restrict__ dst = static_cast<T *>(a.dst);
     const int N = g.nx * g.ny * g.nz;
@@ -748,7 +756,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
     if constexpr (MODE == 2) {
         double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         for (int b = blockIdx.x; b < a.g.nblocks; b += gridDim.x) {
-            const Tile t = tile_of<1>(a.g, b, a.g.ntx);
+            const Tile t = tile_of(a.g, b);
             if (!t.valid) continue;
             LT lk[1] = {0};
             if (MASK) {
@@ -766,7 +774,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
         }
         block_sum_store<5>(acc, a.partials + (size_t)blockIdx.x * 5);
     } else {
-        const Tile t = tile_of<1>(a.g, (int)blockIdx.x, a.g.ntx);
+        const Tile t = tile_of(a.g, (int)blockIdx.x);
         if (!t.valid) return;
         LT lk[1] = {0};
         bool solid = false;
@@ -819,7 +827,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
     const Geometry &g = a.g;
     const Physics &p = a.ph;
     const int bid = a.remap ? xcd_remap((int)blockIdx.x, g.nblocks) : (int)blockIdx.x;
-    const Tile t = tile_of<1>(g, bid, g.ntx);
+    const Tile t = tile_of(g, bid);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     LT lk[1] = {0};
     bool solid = false;
@@ -929,7 +937,7 @@ template <int LAT>
 __global__ __launch_bounds__(kBlock) void k_seed(Geometry g, float value, int axis, float *lam)
 {
     using L = Lat<LAT>;
-    const Tile t = tile_of<1>(g, (int)blockIdx.x, g.ntx);
+    const Tile t = tile_of(g, (int)blockIdx.x);
     if (!t.valid) return;
     const bool solid = g.mask && g.mask[t.own];
 #pragma unroll
@@ -948,8 +956,10 @@ hipError_t step_v(int force, const StepArgs &a, hipStream_t st)
     const bool mask = a.links != nullptr, soft = a.g.s != nullptr;
     const int ntx = (a.g.nx + kBlock * V - 1) / (kBlock * V);
     const int nblocks = ntx * a.g.ny * a.g.nz;
+    const FastDiv div_ntx = make_fastdiv(ntx);
     const dim3 grid(nblocks), block(kBlock);
-#define LBM_STEP(M, S, F) hipLaunchKernelGGL((k_step<LAT, ST, M, S, F, V>), grid, block, 0, st, a, ntx, nblocks)
+#define LBM_STEP(M, S, F) \
+    hipLaunchKernelGGL((k_step<LAT, ST, M, S, F, V>), grid, block, 0, st, a, ntx, div_ntx, nblocks)
 #define LBM_STEP_F(M, S)   \
     if (force == 0)        \
         LBM_STEP(M, S, 0); \
