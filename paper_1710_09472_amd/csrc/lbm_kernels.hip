@@ -83,6 +83,18 @@ struct Codec<LBM_BF16> {
     static __device__ __forceinline__ T enc(float f, float) { return (T)f; }
 };
 
+// Where a bounced population is kept between steps (halfway bounce-back: the value
+// pulled into fluid x as population q, when x - e_q is solid, is f*_qbar(x)):
+// * own slot (FP32): it stays in slot qbar of x, where the step stores it anyway, and
+//   the pull at x reloads it from there for the links of x;
+// * solid slot (16-bit): the step also stores it in slot q of the solid node x - e_q,
+//   so every pull is a plain read of x - e_q and waits on no link mask.
+// Measured on MI355X: the solid slot wins where both state buffers stay in the 256 MB
+// Infinity Cache (16-bit 2048^2 disks 1.3x); with FP32 buffers beyond it, its scattered
+// partial-line stores cost more than the reloads (FP32 2048^2 disks 0.89x).
+template <int ST>
+constexpr bool kSolidSlotBB = ST != LBM_F32;
+
 template <int ST, int V>
 struct VecT {
     typedef typename Codec<ST>::T type __attribute__((ext_vector_type(V)));
@@ -242,47 +254,81 @@ __device__ __forceinline__ Tile tile_of(const Geometry &g, int bid, int ntx, Fas
 
 __device__ __forceinline__ Tile tile_of(const Geometry &g, int bid) { return tile_of<1>(g, bid, g.ntx, g.div_ntx); }
 
-// Pull the pre-collision deviations of the V nodes of tile t; lk holds their link masks.
+// Source of the pull of population q into node x0 + i of tile t: the row of x - e_q
+// (element offset of its first node) and the x index within that row.
+struct PullRows {
+    int ym, yp, zm, zp;
+    unsigned x0, xl, xr;
+};
+
+template <int V>
+__device__ __forceinline__ PullRows pull_rows(const Geometry &g, const Tile &t)
+{
+    PullRows r;
+    r.ym = wrapm(t.y, g.ny);
+    r.yp = wrapp(t.y, g.ny);
+    r.zm = wrapm(t.z, g.nz);
+    r.zp = wrapp(t.z, g.nz);
+    // lane offsets are unsigned 32-bit, so accesses use a scalar base and one VGPR offset
+    r.x0 = (unsigned)t.x0;
+    r.xl = t.x0 == 0 ? (unsigned)(g.nx - 1) : r.x0 - 1u;
+    r.xr = t.x0 + V >= g.nx ? 0u : r.x0 + (unsigned)V;
+    return r;
+}
+
+template <int LAT, int q>
+__device__ __forceinline__ size_t pull_row(const Geometry &g, const Tile &t, const PullRows &r)
+{
+    using L = Lat<LAT>;
+    const int sy = L::ey[q] > 0 ? r.ym : (L::ey[q] < 0 ? r.yp : t.y);
+    const int sz = L::ez[q] > 0 ? r.zm : (L::ez[q] < 0 ? r.zp : t.z);
+    return (size_t)q * g.stride + (size_t)g.nx * (sy + g.ny * sz);
+}
+
+template <int LAT, int q, int V>
+__device__ __forceinline__ unsigned pull_x(const PullRows &r, int i)
+{
+    using L = Lat<LAT>;
+    if constexpr (L::ex[q] > 0) return i == 0 ? r.xl : r.x0 + (unsigned)(i - 1);
+    else if constexpr (L::ex[q] < 0) return i == V - 1 ? r.xr : r.x0 + (unsigned)(i + 1);
+    else return r.x0 + (unsigned)i;
+}
+
+// Pull the pre-collision deviations of the V nodes of tile t (link masks lk). With the
+// solid-slot convention every pull is a plain read of x - e_q; with the own-slot one the
+// populations whose source x - e_q is solid are then reloaded from slot qbar of x.
 template <int LAT, int ST, bool MASK, int V>
 __device__ __forceinline__ void gather_tile(const Geometry &g, const typename Codec<ST>::T *__restrict__ src,
                                             float inv_scale, const Tile &t,
                                             const typename LinkMask<LAT>::T *lk, float (&d)[V][Lat<LAT>::Q])
 {
     using L = Lat<LAT>;
-    const int nx = g.nx;
-    const int ym = wrapm(t.y, g.ny), yp = wrapp(t.y, g.ny);
-    const int zm = wrapm(t.z, g.nz), zp = wrapp(t.z, g.nz);
-    // lane offsets are unsigned 32-bit, so loads use a scalar base and one VGPR offset
-    const unsigned x0 = (unsigned)t.x0;
-    const unsigned xl = t.x0 == 0 ? (unsigned)(nx - 1) : x0 - 1u;
-    const unsigned xr = t.x0 + V >= nx ? 0u : x0 + (unsigned)V;
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) {
-        const int sy = L::ey[q] > 0 ? ym : (L::ey[q] < 0 ? yp : t.y);
-        const int sz = L::ez[q] > 0 ? zm : (L::ez[q] < 0 ? zp : t.z);
-        const typename Codec<ST>::T *base = src + (size_t)q * g.stride + (size_t)nx * (sy + g.ny * sz);
-        if (L::ex[q] == 0) {
+    const PullRows r = pull_rows<V>(g, t);
+    for_q<L::Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const typename Codec<ST>::T *base = src + pull_row<LAT, q>(g, t, r);
+        if constexpr (L::ex[q] == 0) {
             float f[V];
-            vload<ST, V>(at32(base, x0), inv_scale, f);
+            vload<ST, V>(at32(base, r.x0), inv_scale, f);
 #pragma unroll
             for (int i = 0; i < V; ++i) d[i][q] = f[i];
-        } else if (V == 1) {
-            d[0][q] = Codec<ST>::dec(*at32(base, L::ex[q] > 0 ? xl : xr), inv_scale);
-        } else if (L::ex[q] > 0) {  // from x - 1
+        } else if constexpr (V == 1) {
+            d[0][q] = Codec<ST>::dec(*at32(base, L::ex[q] > 0 ? r.xl : r.xr), inv_scale);
+        } else if constexpr (L::ex[q] > 0) {  // from x - 1
             float f[V];
-            vload<ST, V>(at32(base, x0), inv_scale, f);
-            d[0][q] = Codec<ST>::dec(*at32(base, xl), inv_scale);
+            vload<ST, V>(at32(base, r.x0), inv_scale, f);
+            d[0][q] = Codec<ST>::dec(*at32(base, r.xl), inv_scale);
 #pragma unroll
             for (int i = 1; i < V; ++i) d[i][q] = f[i - 1];
         } else {  // from x + 1
             float f[V];
-            vload<ST, V>(at32(base, x0), inv_scale, f);
+            vload<ST, V>(at32(base, r.x0), inv_scale, f);
 #pragma unroll
             for (int i = 0; i < V - 1; ++i) d[i][q] = f[i + 1];
-            d[V - 1][q] = Codec<ST>::dec(*at32(base, xr), inv_scale);
+            d[V - 1][q] = Codec<ST>::dec(*at32(base, r.xr), inv_scale);
         }
-    }
-    if (MASK) {
+    });
+    if constexpr (MASK && !kSolidSlotBB<ST>) {
         // one branch for the whole tile: most tiles have no solid neighbour at all
         typename LinkMask<LAT>::T any = 0;
 #pragma unroll
@@ -538,28 +584,30 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, int ntx, FastDiv di
     const int bid = a.remap ? xcd_remap((int)blockIdx.x, nblocks) : (int)blockIdx.x;
     const Tile t = tile_of<V>(a.g, bid, ntx, div_ntx);
     LT lk[V];
-    bool fluid[V];
-    bool all_fluid = true;
     if (MASK) {
         load_links<LAT, V>(static_cast<const LT *>(a.links), t.own, lk);
         bool any_fluid = false;
 #pragma unroll
-        for (int i = 0; i < V; ++i) {
-            fluid[i] = !(lk[i] & LinkMask<LAT>::solid);
-            any_fluid = any_fluid || fluid[i];
-            all_fluid = all_fluid && fluid[i];
-        }
+        for (int i = 0; i < V; ++i) any_fluid = any_fluid || !(lk[i] & LinkMask<LAT>::solid);
         if (!any_fluid) return;
     }
     float d[V][L::Q];
-    // stored units throughout: no decode or encode scaling
-    gather_tile<LAT, ST, MASK, V>(a.g, static_cast<const T *>(a.src), 1.f, t, lk, d);
+    gather_tile<LAT, ST, MASK, V>(a.g, static_cast<const T *>(a.src), 1.f, t, lk, d);  // stored units throughout
     float sv[V];
     if (SOFT) vload<LBM_F32, V>(at32(a.g.s, (unsigned)t.own), 1.f, sv);
     float o[V][L::Q];
 #pragma unroll
     for (int i = 0; i < V; ++i) collide<LAT, SOFT, FORCE>(a.ph, d[i], SOFT ? sv[i] : 0.f, o[i]);
     if (!t.valid) return;
+    bool fluid[V];
+    bool all_fluid = true;
+    LT links = 0;  // union of the solid-neighbour bits of the fluid nodes
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        fluid[i] = !MASK || !(lk[i] & LinkMask<LAT>::solid);
+        all_fluid = all_fluid && fluid[i];
+        if (MASK && fluid[i]) links |= lk[i];
+    }
     T *__restrict__ dst = static_cast<T *>(a.dst);
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
@@ -574,6 +622,21 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, int ntx, FastDiv di
             for (int i = 0; i < V; ++i)
                 if (fluid[i]) *at32(p, (unsigned)i) = Codec<ST>::enc(o[i][q], 1.f);
         }
+    }
+    if (MASK && kSolidSlotBB<ST> && links) {
+        // solid-slot bounce-back: where x - e_q is solid, the value the next step pulls
+        // into x as population q is f*_qbar(x); store it in slot q of that solid node
+        const PullRows r = pull_rows<V>(a.g, t);
+        for_q<L::Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            if constexpr (q != 0) {
+                T *row = dst + pull_row<LAT, q>(a.g, t, r);
+#pragma unroll
+                for (int i = 0; i < V; ++i)
+                    if (fluid[i] && ((lk[i] >> q) & 1u))
+                        *at32(row, pull_x<LAT, q, V>(r, i)) = Codec<ST>::enc(o[i][L::opp[q]], 1.f);
+            }
+        });
     }
 }
 
@@ -602,17 +665,19 @@ __global__ __launch_bounds__(kBlock) void k_links(Geometry g, typename LinkMask<
 }
 
 // ---------------------------------------------------------------------------------
-// K2: initial state. The stored state is post-collision, so node x holds, for each q,
-// the value that the next pull delivers: f^eq_q(x + e_q) when x + e_q is fluid, or
-// f^eq_qbar(x) when it is solid (bounced back).
+// K2: initial state. The stored state is post-collision and the next step pulls slot q
+// of node y into y + e_q, so node y holds in slot q the equilibrium deviation
+// f^eq_q(y + e_q) when y + e_q is fluid. A bounced value (y + e_q solid, pulled back into
+// y as population qbar) is f^eq_qbar(y): in slot q of y itself (own slot), or in slot
+// qbar of the solid node y + e_q (solid slot). Slots never read hold 0.
 // ---------------------------------------------------------------------------------
 template <int LAT, int q>
 __device__ __forceinline__ float deq_moving(const Physics &p, float drho, float rho, const float *j,
-                                            const float *U, float U2, float sign = 1.f)
+                                            const float *U, float U2)
 {
     constexpr int k = shell<LAT, q>();
-    const float eu = sign * edot<LAT, q>(U);
-    const float ej = sign * edot<LAT, q>(j);
+    const float eu = edot<LAT, q>(U);
+    const float ej = edot<LAT, q>(j);
     return p.what[k] * drho + p.lam[k] * ej + p.what[k] * rho * (p.Bc * eu * eu + p.Cp[k] * U2);
 }
 
@@ -627,11 +692,6 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a)
     if (!t.valid) return;
     T *__restrict__ dst = static_cast<T *>(a.dst);
     const int N = g.nx * g.ny * g.nz;
-    if (g.mask && g.mask[t.own]) {
-#pragma unroll
-        for (int q = 0; q < L::Q; ++q) dst[q * g.stride + t.own] = Codec<ST>::enc(0.f, p.scale);
-        return;
-    }
     const int xm = wrapm(t.x0, g.nx), xp = wrapp(t.x0, g.nx);
     const int ym = wrapm(t.y, g.ny), yp = wrapp(t.y, g.ny);
     const int zm = wrapm(t.z, g.nz), zp = wrapp(t.z, g.nz);
@@ -648,14 +708,19 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a)
         }
         U2 = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
     };
-    float drho0, rho0, j0[3], U0[3], U20;
-    node_state(t.own, drho0, rho0, j0, U0, U20);
-    float sum_eq = 0.f;
-    for_q<L::Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        if constexpr (q != 0) sum_eq += deq_moving<LAT, q>(p, drho0, rho0, j0, U0, U20);
-    });
-    dst[t.own] = Codec<ST>::enc(drho0 - sum_eq, p.scale);
+    const bool own_solid = g.mask && g.mask[t.own];
+    float dev0 = 0.f, drho0 = 0.f, rho0 = 0.f, j0[3] = {0.f, 0.f, 0.f}, U0[3] = {0.f, 0.f, 0.f}, U20 = 0.f;
+    if (!own_solid) {
+        // rest population by closure, so that the deviations of the node sum to drho
+        node_state(t.own, drho0, rho0, j0, U0, U20);
+        float sum_eq = 0.f;
+        for_q<L::Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            if constexpr (q != 0) sum_eq += deq_moving<LAT, q>(p, drho0, rho0, j0, U0, U20);
+        });
+        dev0 = drho0 - sum_eq;
+    }
+    dst[t.own] = Codec<ST>::enc(dev0, p.scale);
     for_q<L::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         if constexpr (q != 0) {
@@ -663,13 +728,14 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a)
             const int ty = L::ey[q] > 0 ? yp : (L::ey[q] < 0 ? ym : t.y);
             const int tz = L::ez[q] > 0 ? zp : (L::ez[q] < 0 ? zm : t.z);
             const int tn = tx + g.nx * (ty + g.ny * tz);
-            float dev;
-            if (g.mask && g.mask[tn]) {
-                dev = deq_moving<LAT, q>(p, drho0, rho0, j0, U0, U20, -1.f);  // f^eq of the opposite direction
-            } else {
+            float dev = 0.f;
+            const bool tn_solid = g.mask && g.mask[tn];
+            if (!tn_solid && (kSolidSlotBB<ST> || !own_solid)) {
                 float dr, r, j[3], U[3], U2;
                 node_state(tn, dr, r, j, U, U2);
                 dev = deq_moving<LAT, q>(p, dr, r, j, U, U2);
+            } else if (tn_solid && !kSolidSlotBB<ST> && !own_solid) {
+                dev = deq_moving<LAT, L::opp[q]>(p, drho0, rho0, j0, U0, U20);  // bounced, own slot
             }
             dst[q * g.stride + t.own] = Codec<ST>::enc(dev, p.scale);
         }
