@@ -97,7 +97,8 @@ def timed_steps(sim, steps: int, warmup: int):
 
 def adjoint_ratio(wl, steps: int, warmup: int):
     """Average time of one adjoint step (reverse pull, transposed collision and force,
-    FP64 block partials for dJ/dE and dJ/dtau) relative to one forward step."""
+    FP64 per-wave partials of dJ/dE and dJ/dtau held across steps and reduced on the
+    last one) relative to one forward step."""
     import torch
     from paper_1710_09472_amd.lbm import Simulation
 
@@ -112,7 +113,7 @@ def adjoint_ratio(wl, steps: int, warmup: int):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(sim.stream)
     for i in range(steps):
-        sim.adjoint_step(state, lam[i % 2], lam[(i + 1) % 2], None, gsc)
+        sim.adjoint_step(state, lam[i % 2], lam[(i + 1) % 2], None, gsc if i == steps - 1 else None)
     e1.record(sim.stream)
     torch.cuda.synchronize()
     t_adj = e0.elapsed_time(e1) * 1e-3 / steps

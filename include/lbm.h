@@ -161,7 +161,8 @@ int lbm_set_tau(lbm_t h, double tau);
 
 /* Adjoint seed for J = (1/norm) sum over fluid nodes x and a of f_a(x, T) xi_a[axis]:
  * lam[a*stride + n] = xi_a[axis]/norm at fluid nodes, 0 at solids. lam: device float
- * buffer of adjoint_bytes. Async. */
+ * buffer of adjoint_bytes. Starts a reverse pass: held dJ/dE, dJ/dtau contributions of
+ * lbm_adjoint_step are discarded. Async. */
 int lbm_adjoint_seed(lbm_t h, int axis, double norm, float *lam);
 
 /* One reverse step of the discrete adjoint of lbm_step (not in the paper).
@@ -169,7 +170,11 @@ int lbm_adjoint_seed(lbm_t h, int axis, double norm, float *lam);
  *             handle held before the forward step t -> t+1)
  *   lam_in  : dJ/df(t+1) (adjoint_bytes); lam_out: dJ/df(t) (distinct buffer)
  *   grad_s  : device float[N]; += dJ/ds through this step; may be NULL
- *   grad_scalars : device double[4]; += (dJ/dE_x, dJ/dE_y, dJ/dE_z, dJ/dtau); may be NULL
+ *   grad_scalars : device double[4]; += (dJ/dE_x, dJ/dE_y, dJ/dE_z, dJ/dtau) of this step
+ *             and of every earlier step since the last call that passed one. NULL keeps
+ *             this step's contribution as FP64 per-wave partials in the workspace (no
+ *             reduction kernels), to be added by a later call; lbm_adjoint_seed discards
+ *             contributions still held (a new reverse pass).
  * Async. */
 int lbm_adjoint_step(lbm_t h, const void *state, const float *lam_in, float *lam_out,
                      float *grad_s, double *grad_scalars);

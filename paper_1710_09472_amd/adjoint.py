@@ -77,7 +77,8 @@ def adjoint_gradients(pb: Problem, sim: Simulation, cps):
         for k in range(1, n):
             sim.step_from(seg_bufs[k - 1], seg_bufs[k])
         for k in range(n - 1, -1, -1):
-            sim.adjoint_step(seg_bufs[k], lam[cur], lam[cur ^ 1], gs, gsc)
+            # dJ/dE, dJ/dtau stay as per-block partials until the last step of the pass
+            sim.adjoint_step(seg_bufs[k], lam[cur], lam[cur ^ 1], gs, gsc if (i == 0 and k == 0) else None)
             cur ^= 1
     return gsc[:3].clone(), gsc[3].clone(), gs, lam[cur]
 

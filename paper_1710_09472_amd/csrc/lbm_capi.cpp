@@ -43,6 +43,7 @@ struct lbm_s {
     Physics ph{};
     void *links = nullptr;  // per-node link masks inside the work buffer
     bool initialized = false;
+    bool adj_held = false;  // work_adj holds adjoint contributions not yet reduced
     std::string err;
 };
 
@@ -97,6 +98,25 @@ struct Sizes {
     size_t state, work, adjoint;
 };
 
+// Workspace layout (bytes from its start): FP64 totals; per-block partials of the
+// reductions; second-stage scratch; link masks (256-byte aligned); FP64 per-block
+// partials of dJ/dE, dJ/dtau, one per wave, held across adjoint steps (256-byte aligned).
+struct WorkLayout {
+    size_t parts, stage, links, adj, total;
+};
+
+WorkLayout work_layout(int nblocks, int stride)
+{
+    WorkLayout w;
+    const size_t parts = std::max((size_t)kReduceBlocks * 5, (size_t)nblocks * 4);
+    w.parts = 64;
+    w.stage = w.parts + parts * sizeof(double);
+    w.links = (w.stage + (size_t)kReduceStage * 8 * sizeof(double) + 255) / 256 * 256;
+    w.adj = (w.links + (size_t)stride * 4 + 255) / 256 * 256;
+    w.total = w.adj + (size_t)nblocks * (kBlock / 64) * 4 * sizeof(double);
+    return w;
+}
+
 // Validation shared by create and the size query. Writes the message through fail().
 int validate(const lbm_params *p, lbm_t h, Sizes *sz)
 {
@@ -129,9 +149,7 @@ int validate(const lbm_params *p, lbm_t h, Sizes *sz)
         sz->nblocks = sz->ntx * p->ny * p->nz;
         sz->state = (size_t)Q * (size_t)sz->stride * elem_size(p->storage);
         sz->adjoint = (size_t)Q * (size_t)sz->stride * sizeof(float);
-        const size_t parts = std::max((size_t)kReduceBlocks * 5, (size_t)sz->nblocks * 4);
-        sz->work = 64 + parts * sizeof(double) + (size_t)kReduceStage * 8 * sizeof(double);
-        sz->work = (sz->work + 255) / 256 * 256 + (size_t)sz->stride * 4;  // link masks
+        sz->work = work_layout(sz->nblocks, sz->stride).total;
     }
     return LBM_OK;
 }
@@ -224,21 +242,10 @@ int force_level(const lbm_t h) { return has_B(h) ? 2 : (has_E(h) ? 1 : 0); }
 const void *links_of(const lbm_t h) { return h->mask ? h->links : nullptr; }
 
 double *work_out(lbm_t h) { return reinterpret_cast<double *>(h->work); }
-double *work_parts(lbm_t h) { return reinterpret_cast<double *>(h->work + 64); }
-// link masks after the reduction scratch (256-byte aligned)
-void *work_links(lbm_t h)
-{
-    const size_t parts = std::max((size_t)kReduceBlocks * 5, (size_t)h->g.nblocks * 4);
-    size_t off = 64 + parts * sizeof(double) + (size_t)kReduceStage * 8 * sizeof(double);
-    off = (off + 255) / 256 * 256;
-    return h->work + off;
-}
-// second-stage scratch after the largest partials array
-double *work_stage(lbm_t h)
-{
-    const size_t parts = std::max((size_t)kReduceBlocks * 5, (size_t)h->g.nblocks * 4);
-    return reinterpret_cast<double *>(h->work + 64 + parts * sizeof(double));
-}
+double *work_parts(lbm_t h) { return reinterpret_cast<double *>(h->work + work_layout(h->g.nblocks, h->stride).parts); }
+double *work_stage(lbm_t h) { return reinterpret_cast<double *>(h->work + work_layout(h->g.nblocks, h->stride).stage); }
+void *work_links(lbm_t h) { return h->work + work_layout(h->g.nblocks, h->stride).links; }
+double *work_adj(lbm_t h) { return reinterpret_cast<double *>(h->work + work_layout(h->g.nblocks, h->stride).adj); }
 
 }  // namespace
 
@@ -530,6 +537,7 @@ int lbm_adjoint_seed(lbm_t h, int axis, double norm, float *lam)
     if (!(norm != 0.0) || !std::isfinite(norm)) return fail(h, LBM_EINVAL, "norm must be finite and non-zero");
     const hipError_t e = launch_seed(h->p.lattice, h->g, (float)(1.0 / (h->k.cs * norm)), axis, lam, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "seed kernel launch");
+    h->adj_held = false;  // a new reverse pass
     return LBM_OK;
 }
 
@@ -548,12 +556,16 @@ int lbm_adjoint_step(lbm_t h, const void *state, const float *lam_in, float *lam
     a.lam_in = lam_in;
     a.lam_out = lam_out;
     a.grad_s = grad_s;
-    a.partials = work_parts(h);
+    a.partials = work_adj(h);
+    a.accumulate = h->adj_held ? 1 : 0;
     hipError_t e = launch_adjoint(h->p.lattice, h->p.storage, has_B(h), a, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "adjoint kernel launch");
+    h->adj_held = true;
     if (grad_scalars) {
-        e = launch_reduce_final(work_parts(h), h->g.nblocks, 4, grad_scalars, 1, h->stream, work_stage(h));
+        e = launch_reduce_final(work_adj(h), h->g.nblocks * (kBlock / 64), 4, grad_scalars, 1, h->stream,
+                                work_stage(h));
         if (e != hipSuccess) return hip_fail(h, e, "reduce kernel launch");
+        h->adj_held = false;
     }
     return LBM_OK;
 }

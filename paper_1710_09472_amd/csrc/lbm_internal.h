@@ -136,7 +136,8 @@ struct AdjointArgs {
     const float *lam_in;
     float *lam_out;
     float *grad_s;    // nullable
-    double *partials; // per-block (dE_x, dE_y, dE_z, dtau)
+    double *partials; // per-wave (dE_x, dE_y, dE_z, dtau)
+    int accumulate;   // add this step's wave sums to partials instead of overwriting
 };
 
 // Launchers (lbm_kernels.hip). Each returns hipSuccess or the launch error.

@@ -435,63 +435,6 @@ __device__ __forceinline__ Macro<LAT> macro(const Physics &p, const float *d)
     return m;
 }
 
-template <int LAT, int FORCE>
-__device__ __forceinline__ void collide_node(const Physics &p, const Macro<LAT> &m, const float *d, float *o,
-                                             float *deq_out = nullptr, float *sig_out = nullptr)
-{
-    using L = Lat<LAT>;
-    const float om = p.omega;
-    float wd[3], wr[3], cu[3], sk[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        wd[k] = p.what[k] * m.drho;
-        wr[k] = p.what[k] * m.rho;
-        cu[k] = p.Cp[k] * m.U2;
-    }
-    float W[3] = {0.f, 0.f, 0.f};
-    if constexpr (FORCE >= 1) {
-        float UE = m.U[0] * p.E[0] + m.U[1] * p.E[1];
-        if constexpr (L::D == 3) UE += m.U[2] * p.E[2];
-        UE *= p.cs;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) sk[k] = p.C2[k] * UE;
-    }
-    if constexpr (FORCE == 2) {
-        W[0] = p.B[1] * m.U[2] - p.B[2] * m.U[1];
-        W[1] = p.B[2] * m.U[0] - p.B[0] * m.U[2];
-        W[2] = p.B[0] * m.U[1] - p.B[1] * m.U[0];
-    }
-    float sum_eq = 0.f;
-    for_q<L::Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        if constexpr (q != 0) {
-            constexpr int k = shell<LAT, q>();
-            const float eu = edot<LAT, q>(m.U);
-            const float ej = edot<LAT, q>(m.j);
-            const float quad = __builtin_fmaf(p.Bc * eu, eu, cu[k]);
-            const float deq = __builtin_fmaf(wr[k], quad, __builtin_fmaf(p.lam[k], ej, wd[k]));
-            sum_eq = (q == 1) ? deq : sum_eq + deq;
-            float v = __builtin_fmaf(om, deq - d[q], d[q]);
-            if constexpr (FORCE >= 1) {
-                float sig = __builtin_fmaf(p.c2q[q], eu, p.c1q[q] + sk[k]);
-                if constexpr (FORCE == 2) sig = __builtin_fmaf(p.C2[k], edot<LAT, q>(W), sig);
-                v = __builtin_fmaf(wr[k], sig, v);
-                if (sig_out) sig_out[q] = sig;
-            }
-            o[q] = v;
-            if (deq_out) deq_out[q] = deq;
-        }
-    });
-    const float deq0 = m.drho - sum_eq;
-    float v0 = __builtin_fmaf(om, deq0 - d[0], d[0]);
-    if constexpr (FORCE >= 1) {
-        v0 = __builtin_fmaf(wr[0], sk[0], v0);
-        if (sig_out) sig_out[0] = sk[0];
-    }
-    o[0] = v0;
-    if (deq_out) deq_out[0] = deq0;
-}
-
 // Forward collision of one node in stored units (deviations times the storage scale S):
 // BGK relaxation toward the reduced equilibrium plus the Lorentz source, with omega and S
 // folded into per-shell constants,
@@ -745,6 +688,31 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a)
 // ---------------------------------------------------------------------------------
 // Block reductions.
 // ---------------------------------------------------------------------------------
+// Sum of v over the 64 lanes of a wave, complete in lane 63, with DPP lane moves of the
+// CDNA ISA (no LDS): quad permutes xor 1 and xor 2, half-row and row mirrors (every lane
+// then holds its 16-lane row sum), then row broadcasts of lanes 15 and 31 into the rows
+// above. Lanes of rows a move leaves out add 0. Needs all 64 lanes active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_add(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWS, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWS, 0xF, false);
+    return v + __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double wave_sum_last_lane(double v)
+{
+    v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v = dpp_add<0x141, 0xF>(v);  // row_half_mirror
+    v = dpp_add<0x140, 0xF>(v);  // row_mirror
+    v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// out[c] = sum over the block of v[c].
 template <int NC>
 __device__ __forceinline__ void block_sum_store(double *v, double *out)
 {
@@ -895,6 +863,15 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
     const int bid = a.remap ? xcd_remap((int)blockIdx.x, g.nblocks) : (int)blockIdx.x;
     const Tile t = tile_of(g, bid);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    // One partial per wave, written by its last lane. The accumulated value is read first
+    // (a wave-uniform address: scalar registers), so its latency overlaps the pulls below.
+    const bool last_lane = (threadIdx.x & 63) == 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    double *part = a.partials + ((size_t)blockIdx.x * (kBlock / 64) + wave) * 4;
+    double prev[4] = {0.0, 0.0, 0.0, 0.0};
+    if (a.accumulate)
+        for (int c = 0; c < 4; ++c) prev[c] = part[c];
+    const float gs_prev = (SOFT && a.grad_s && t.valid) ? *at32(a.grad_s, (unsigned)t.own) : 0.f;
     LT lk[1] = {0};
     bool solid = false;
     if (MASK && t.valid) {
@@ -926,35 +903,57 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
         }
         const float s = SOFT ? *at32(g.s, (unsigned)t.own) : 0.f;
         const Macro<LAT> m = macro<LAT>(p, d[0]);
-        float dst[L::Q], deq[L::Q], sig[L::Q];
-        collide_node<LAT, MAG ? 2 : 1>(p, m, d[0], dst, deq, sig);
         const float inv_cs = p.cs * p.inv_cs2;
         const float om = p.omega;
         const float inv_rho = __builtin_amdgcn_rcpf(m.rho);
         const float one_s = 1.f - s;
+        // Forward quantities of the node, per shell k: what_k drho, what_k rho, Cp_k U^2 and
+        // the source's 2 C_k c_s (U.E); W = U x B.
+        float wd[3], wr[3], cu[3], sk[3] = {0.f, 0.f, 0.f}, W[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            wd[k] = p.what[k] * m.drho;
+            wr[k] = p.what[k] * m.rho;
+            cu[k] = p.Cp[k] * m.U2;
+        }
+        {
+            float UE = m.U[0] * p.E[0] + m.U[1] * p.E[1];
+            if constexpr (L::D == 3) UE += m.U[2] * p.E[2];
+            UE *= p.cs;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) sk[k] = p.C2[k] * UE;
+        }
+        if (MAG) {
+            W[0] = p.B[1] * m.U[2] - p.B[2] * m.U[1];
+            W[1] = p.B[2] * m.U[0] - p.B[0] * m.U[2];
+            W[2] = p.B[0] * m.U[1] - p.B[1] * m.U[0];
+        }
         // Sums over q, with the q-independent factors applied once at the end:
         //   Ee = sum hw (A + 2 Bc e.U) e,  Ve = sum hw a1 e,  Wc = sum hw 2 C_k e,
         //   S1 = sum hw 2 C_k,  S2 = sum hw C_k c_s^2,  R1 = sum h (what rho0 + deq),
         //   R2 = sum hw sigma, with hw = h what_k, a1 = omega (A + 2 Bc e.U) + 2 Bc (e.E)/c_s.
+        // deq, sigma and the post-collision d* of each q are formed inside the loop (as in
+        // the forward step, rest population last by closure), so no per-q arrays stay live.
         float Ee[3] = {0.f, 0.f, 0.f}, Ve[3] = {0.f, 0.f, 0.f}, Wc[3] = {0.f, 0.f, 0.f};
-        float S1 = 0.f, S2 = 0.f, R1 = 0.f, R2 = 0.f, ds = 0.f, dtau = 0.f;
-        float hb[L::Q];
+        float S1 = 0.f, S2 = 0.f, R1 = 0.f, R2 = 0.f, ds = 0.f, dtau = 0.f, sum_eq = 0.f;
         auto acc_e = [](float *acc, float v, int ex, int ey, int ez) {
             if (ex) acc[0] += ex > 0 ? v : -v;
             if (ey) acc[1] += ey > 0 ? v : -v;
             if (ez) acc[2] += ez > 0 ? v : -v;
         };
-        for_q<L::Q>([&](auto qc) {
+        auto terms = [&](auto qc, float deq, float sig) {
             constexpr int q = decltype(qc)::value;
             constexpr int k = shell<LAT, q>();
             constexpr int ex = L::ex[q], ey = L::ey[q], ez = L::ez[q];
             const float h = one_s * gb[q];
-            hb[q] = h;
             const float hw = h * p.what[k];
-            if (SOFT) ds = __builtin_fmaf(gb[q], d[0][L::opp[q]] - dst[q], ds);
-            dtau = __builtin_fmaf(h, d[0][q] - deq[q], dtau);
-            R1 = __builtin_fmaf(h, p.what[k] * p.rho0 + deq[q], R1);
-            R2 = __builtin_fmaf(hw, sig[q], R2);
+            if (SOFT) {
+                const float dstq = __builtin_fmaf(wr[k], sig, __builtin_fmaf(om, deq - d[0][q], d[0][q]));
+                ds = __builtin_fmaf(gb[q], d[0][L::opp[q]] - dstq, ds);
+            }
+            dtau = __builtin_fmaf(h, d[0][q] - deq, dtau);
+            R1 = __builtin_fmaf(h, p.what[k] * p.rho0 + deq, R1);
+            R2 = __builtin_fmaf(hw, sig, R2);
             S1 = __builtin_fmaf(hw, p.C2[k], S1);
             S2 = __builtin_fmaf(hw, p.Cp[k], S2);
             if constexpr (q != 0) {
@@ -965,7 +964,22 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
                 acc_e(Ve, hw * a1, ex, ey, ez);
                 if (MAG) acc_e(Wc, hw * p.C2[k], ex, ey, ez);
             }
+        };
+        for_q<L::Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            if constexpr (q != 0) {
+                constexpr int k = shell<LAT, q>();
+                const float eu = edot<LAT, q>(m.U);
+                const float ej = edot<LAT, q>(m.j);
+                const float quad = __builtin_fmaf(p.Bc * eu, eu, cu[k]);
+                const float deq = __builtin_fmaf(wr[k], quad, __builtin_fmaf(p.lam[k], ej, wd[k]));
+                sum_eq = (q == 1) ? deq : sum_eq + deq;
+                float sig = __builtin_fmaf(p.c2q[q], eu, p.c1q[q] + sk[k]);
+                if (MAG) sig = __builtin_fmaf(p.C2[k], edot<LAT, q>(W), sig);
+                terms(qc, deq, sig);
+            }
         });
+        terms(std::integral_constant<int, 0>{}, m.drho - sum_eq, sk[0]);
         // dJ/dE_i = sum hw [(A + 2 Bc e.U) e_i / c_s + 2 C_k c_s U_i]  (times rho below)
         float dE[3], V[3];
 #pragma unroll
@@ -985,17 +999,20 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
         const float one_om = 1.f - om;
         for_q<L::Q>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            float out = __builtin_fmaf(one_om, hb[q], base + edot<LAT, q>(Vs));
+            float out = __builtin_fmaf(one_om, one_s * gb[q], base + edot<LAT, q>(Vs));
             if (SOFT) out = __builtin_fmaf(s, gb[L::opp[q]], out);
             *at32(a.lam_out + (size_t)q * g.stride, (unsigned)t.own) = out;
         });
-        if (SOFT && a.grad_s) a.grad_s[t.own] += ds;
+        if (SOFT && a.grad_s) *at32(a.grad_s, (unsigned)t.own) = gs_prev + ds;
         acc[0] = (double)m.rho * (double)dE[0];
         acc[1] = (double)m.rho * (double)dE[1];
         acc[2] = (double)m.rho * (double)dE[2];
         acc[3] = (double)(om * om) * (double)dtau;
     }
-    block_sum_store<4>(acc, a.partials + (size_t)blockIdx.x * 4);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = wave_sum_last_lane(acc[c]);
+    if (last_lane)
+        for (int c = 0; c < 4; ++c) part[c] = prev[c] + acc[c];
 }
 
 // Adjoint seed: lam(a, n) = e_a[axis] * value at fluid nodes (value = 1/(c_s norm)).

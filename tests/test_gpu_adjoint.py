@@ -76,6 +76,39 @@ def test_adjoint_matches_oracle(case):
         assert err_s < TOL, err_s
 
 
+def test_held_partials_match_per_step_reduction():
+    """dJ/dE, dJ/dtau held as per-block partials over the reverse pass (grad_scalars
+    passed on the last step only) equal the per-step reductions up to the order of the
+    FP64 sums; a new seed discards contributions still held."""
+    wl = _wl(CASES[1])
+    T = 6
+    sim = gpu_sim(wl)
+    states = [sim.get_state()]
+    for _ in range(T):
+        sim.step(1)
+        states.append(sim.get_state())
+
+    def reverse(last_only, spoil=False):
+        if spoil:  # a pass that ends without grad_scalars leaves contributions held
+            lam = [sim.adjoint_seed(0, wl.N), sim.new_adjoint()]
+            sim.adjoint_step(states[0], lam[0], lam[1], None, None)
+        lam = [sim.adjoint_seed(0, wl.N), sim.new_adjoint()]
+        gsc = torch.zeros(4, dtype=torch.float64, device="cuda")
+        cur = 0
+        for t in range(T - 1, -1, -1):
+            sim.adjoint_step(states[t], lam[cur], lam[cur ^ 1], None, gsc if (t == 0 or not last_only) else None)
+            cur ^= 1
+        torch.cuda.synchronize()
+        return gsc.cpu().numpy(), lam[cur].clone()
+
+    g_each, lam_each = reverse(False)
+    g_held, lam_held = reverse(True)
+    g_spoil, _ = reverse(True, spoil=True)
+    assert torch.equal(lam_each, lam_held)
+    np.testing.assert_allclose(g_held, g_each, rtol=1e-12, atol=1e-15 * np.abs(g_each).max())
+    np.testing.assert_allclose(g_spoil, g_held, rtol=1e-12, atol=1e-15 * np.abs(g_each).max())
+
+
 def test_autograd_checkpointed_vs_oracle_fd():
     """torch.autograd through MeanCurrent with K = 7 checkpoints over T = 30 steps
     (segments of unequal length) against FP64 central differences of the oracle."""
