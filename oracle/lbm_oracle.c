@@ -16,7 +16,14 @@
  *   - E and B are in xi-units per time step, Delta t = 1;
  *   - walls are halfway (link) bounce-back against solid nodes (mask = 1);
  *   - the optional partial bounce-back g_a = (1-s) f*_a + s f_abar is the
- *     Walsh-Burwinkle-Saar (2009) gray-lattice rule; it is not in the paper.
+ *     Walsh-Burwinkle-Saar (2009) gray-lattice rule; it is not in the paper;
+ *   - the velocity-shift forcing of Sec. 7 (the scheme of the experiments of Sec. 9)
+ *     evaluates f^eq at u + tau a with the macroscopic acceleration a = E + u x B and
+ *     adds no source term;
+ *   - free-slip walls (Sec. 9.4) are the domain planes y = 0, ny-1 (and z = 0, nz-1)
+ *     reflecting specularly: a population pushed into a wall plane keeps its motion
+ *     along the wall and reverses its normal component, arriving beside its emitter;
+ *     if that node is an obstacle it bounces back instead.
  *
  * Layout: full populations (not deviations), f[a*N + n], n = x + nx*(y + ny*z).
  * Rows (y, z) are split over OpenMP threads; that is the only optimisation.
@@ -44,6 +51,8 @@ typedef struct {
     int e[ORC_QMAX][3];     /* integer lattice vectors e_a */
     double xi[ORC_QMAX][3]; /* discrete velocities xi_a = e_a / c_s, Sec. 8 */
     int opp[ORC_QMAX];      /* index of -e_a */
+    int forcing;            /* 0: xi-dependent source term; 1: velocity shift */
+    int slip;               /* free-slip wall planes: bit 0 y, bit 1 z */
 } orc_model;
 
 int orc_model_size(void) { return (int)sizeof(orc_model); }
@@ -111,6 +120,16 @@ int orc_init_model(orc_model *m, int D, int Q, const int *ev, int nx, int ny, in
                 m->opp[a] = b;
         if (m->opp[a] < 0) return -1;
     }
+    return 0;
+}
+
+/* Forcing scheme (0 source, 1 velocity shift) and free-slip planes (bit 0 y, bit 1 z). */
+int orc_set_scheme(orc_model *m, int forcing, int slip)
+{
+    if (forcing != 0 && forcing != 1) return -1;
+    if (slip < 0 || slip > 3 || (m->D == 2 && (slip & 2))) return -1;
+    m->forcing = forcing;
+    m->slip = slip;
     return 0;
 }
 
@@ -203,8 +222,18 @@ void orc_collide_node(const orc_model *m, const double *f, double s, double *g)
 {
     double rho, u[3], feq[ORC_QMAX], S[ORC_QMAX], fs[ORC_QMAX];
     orc_node_moments(m, f, &rho, u);
-    orc_equilibrium(m, rho, u, feq);
-    orc_source(m, rho, u, S);
+    if (m->forcing == 1) {
+        /* velocity shift, eq. (u-update-force-term-eq): f^eq at u + tau a, a = E + u x B */
+        double ub[3], ueq[3];
+        cross3(u, m->B, ub);
+        for (int i = 0; i < 3; ++i) ueq[i] = u[i] + m->tau * (m->E[i] + ub[i]);
+        if (m->D == 2) ueq[2] = 0.0;
+        orc_equilibrium(m, rho, ueq, feq);
+        for (int a = 0; a < m->Q; ++a) S[a] = 0.0;
+    } else {
+        orc_equilibrium(m, rho, u, feq);
+        orc_source(m, rho, u, S);
+    }
     for (int a = 0; a < m->Q; ++a) fs[a] = f[a] - (f[a] - feq[a]) / m->tau + S[a];
     for (int a = 0; a < m->Q; ++a) g[a] = (1.0 - s) * fs[a] + s * f[m->opp[a]];
 }
@@ -234,10 +263,23 @@ void orc_init_state(const orc_model *m, const uint8_t *mask, const double *rho, 
     }
 }
 
+/* index of the vector e with the components of the axes in `flip` (bit 1 y, bit 2 z) reversed */
+static int reflected(const orc_model *m, int a, int flip)
+{
+    const int ex = m->e[a][0], ey = (flip & 1) ? -m->e[a][1] : m->e[a][1];
+    const int ez = (flip & 2) ? -m->e[a][2] : m->e[a][2];
+    for (int b = 0; b < m->Q; ++b)
+        if (m->e[b][0] == ex && m->e[b][1] == ey && m->e[b][2] == ez) return b;
+    return -1;
+}
+
 /*
  * One time step: collide every fluid node, then push each post-collision population
- * g_a(x) to x + e_a (periodic wrap); if x + e_a is solid it returns to x in the
- * opposite direction (halfway bounce-back). Solid nodes hold zero.
+ * g_a(x) to x + e_a (periodic wrap). If x + e_a lies in a free-slip wall plane, the
+ * population is reflected there: it arrives at x + e_a with the wall-axis coordinates
+ * of x, in the direction with those components of e_a reversed. If its destination is
+ * solid (an obstacle), it returns to x in the opposite direction (halfway bounce-back).
+ * Solid nodes (mask = 1; the caller includes the wall planes) hold zero.
  * `s` (per node, may be NULL) is the partial bounce-back fraction.
  */
 void orc_step(const orc_model *m, const uint8_t *mask, const double *s, const double *fin,
@@ -256,13 +298,20 @@ void orc_step(const orc_model *m, const uint8_t *mask, const double *s, const do
                 for (int a = 0; a < Q; ++a) f[a] = fin[a * N + n];
                 orc_collide_node(m, f, s ? s[n] : 0.0, g);
                 for (int a = 0; a < Q; ++a) {
-                    const long d = node_index(m, wrap(x + m->e[a][0], m->nx),
-                                              wrap(y + m->e[a][1], m->ny),
-                                              wrap(z + m->e[a][2], m->nz));
+                    int tx = wrap(x + m->e[a][0], m->nx), ty = wrap(y + m->e[a][1], m->ny);
+                    int tz = wrap(z + m->e[a][2], m->nz), b = a;
+                    const int flip = (((m->slip & 1) && m->e[a][1] != 0 && (ty == 0 || ty == m->ny - 1)) ? 1 : 0) |
+                                     (((m->slip & 2) && m->e[a][2] != 0 && (tz == 0 || tz == m->nz - 1)) ? 2 : 0);
+                    if (flip) {
+                        if (flip & 1) ty = y;
+                        if (flip & 2) tz = z;
+                        b = reflected(m, a, flip);
+                    }
+                    const long d = node_index(m, tx, ty, tz);
                     if (mask && mask[d])
                         fout[m->opp[a] * N + n] = g[a];
                     else
-                        fout[a * N + d] = g[a];
+                        fout[b * N + d] = g[a];
                 }
             }
 }

@@ -79,7 +79,7 @@ class OracleModel:
 
     def __init__(self, lattice: str, nx: int, ny: int, nz: int = 1, tau: float = 0.8,
                  E=(0.0, 0.0, 0.0), B=(0.0, 0.0, 0.0), stats: str = "fd", theta="1/270",
-                 mu: float = 1.0):
+                 mu: float = 1.0, forcing: str = "source", slip: int = 0):
         self.lattice = lattice
         self.D = K.LATTICE_DIM[lattice]
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
@@ -111,6 +111,17 @@ class OracleModel:
         if rc != 0:
             raise RuntimeError("oracle model init failed")
         self._keep = (coef, wn, ev)
+        # forcing: "source" (xi-dependent term of Sec. 7) or "shift" (f^eq at u + tau a);
+        # slip: free-slip wall planes, bit 0 y in {0, ny-1}, bit 1 z in {0, nz-1}
+        self.forcing, self.slip = forcing, int(slip)
+        if lib.orc_set_scheme(self._m, {"source": 0, "shift": 1}[forcing], self.slip) != 0:
+            raise ValueError("forcing must be 'source' or 'shift'; slip 0..1 (2D) or 0..3 (3D)")
+        self.wall = np.zeros(self.N, dtype=np.uint8)
+        zz, yy, _ = np.meshgrid(np.arange(self.nz), np.arange(self.ny), np.arange(self.nx), indexing="ij")
+        if self.slip & 1:
+            self.wall[((yy == 0) | (yy == self.ny - 1)).reshape(-1)] = 1
+        if self.slip & 2:
+            self.wall[((zz == 0) | (zz == self.nz - 1)).reshape(-1)] = 1
 
     # ---------------------------------------------------------------- per node
     def node_moments(self, f):
@@ -142,11 +153,12 @@ class OracleModel:
 
     # ---------------------------------------------------------------- fields
     def _mask(self, mask):
+        """Solid flags: the obstacles of `mask` and the free-slip wall planes."""
         if mask is None:
-            return None
+            return self.wall.copy() if self.slip else None
         m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
         assert m.size == self.N
-        return m
+        return (m | self.wall) if self.slip else m
 
     def _s(self, s):
         if s is None:
@@ -202,7 +214,10 @@ class OracleModel:
 
     def adjoint_step(self, f_t, lam_in, mask=None, s=None, grad_s=None, grad=None):
         """One reverse step. Returns lam_out; accumulates into grad_s (N,) and
-        grad (4,) = (dJ/dEx, dJ/dEy, dJ/dEz, dJ/dtau) when given."""
+        grad (4,) = (dJ/dEx, dJ/dEy, dJ/dEz, dJ/dtau) when given. Source forcing and
+        bounce-back walls only."""
+        if self.forcing != "source" or self.slip:
+            raise NotImplementedError("the oracle adjoint covers the source forcing and bounce-back walls")
         f_t = np.ascontiguousarray(f_t, dtype=np.float64)
         lam_in = np.ascontiguousarray(lam_in, dtype=np.float64)
         out = np.empty_like(lam_in)
