@@ -61,6 +61,20 @@ enum {
     LBM_ESTATE = -5         /* call out of order (e.g. step before init) */
 };
 
+/* Forcing scheme of E and B (Sec. 7):
+ *   LBM_FORCE_SOURCE : the xi-dependent source S_a = (E + xi_a x B) . grad_u f^eq_a added
+ *                      to the BGK update (Sec. 7, forcing-term-integrals-eq);
+ *   LBM_FORCE_SHIFT  : velocity shift, f^eq evaluated at u + tau (E + u x B) and no source
+ *                      (eq. u-update-force-term-eq; the scheme of the runs of Sec. 9). */
+enum { LBM_FORCE_SOURCE = 0, LBM_FORCE_SHIFT = 1 };
+
+/* Free-slip walls (Sec. 9.4): LBM_SLIP_Y makes the planes y = 0 and y = ny-1 solid walls
+ * that reflect specularly (a population keeps its motion along the wall and reverses
+ * the normal component, arriving beside the node that emitted it); LBM_SLIP_Z the
+ * same for z = 0 and z = nz-1. Obstacles of the mask keep halfway bounce-back, also
+ * when a reflection would land on one. */
+enum { LBM_SLIP_Y = 1, LBM_SLIP_Z = 2 };
+
 typedef struct {
     int lattice;        /* LBM_D2V9 or LBM_D3V19 */
     int stats;          /* LBM_FERMI_DIRAC or LBM_HERMITE */
@@ -72,6 +86,8 @@ typedef struct {
     double B[3];        /* magnetic field: rotation angle of u per step */
     double rho0;        /* reference density of the stored deviations (> 0) */
     int dev_scale_log2; /* LBM_F16 only: stored value is d * 2^dev_scale_log2 (0..40) */
+    int forcing;        /* LBM_FORCE_SOURCE or LBM_FORCE_SHIFT */
+    int slip;           /* free-slip wall planes: 0, or LBM_SLIP_Y | LBM_SLIP_Z (3D only) */
 } lbm_params;
 
 /* Constants the library derives from the parameters (host FP64), exposed for
@@ -116,8 +132,9 @@ int lbm_buffer_sizes(const lbm_params *p, size_t *state_bytes, size_t *work_byte
  *   work    : device buffer of work_bytes
  *   stream  : hipStream_t (NULL = default stream)
  * Errors: LBM_EINVAL (tau <= 1/2, bad sizes, B_x/B_y or E_z in 2D, nz != 1 for D2V9,
- * null buffer, F16 scale out of range), LBM_EUNSUPPORTED (non-positive weight),
- * LBM_EDEVICE. On error *out is NULL. */
+ * null buffer, F16 scale out of range, unknown forcing, slip bits other than Y/Z, Z
+ * slip in 2D, a slip axis with fewer than 3 planes), LBM_EUNSUPPORTED (non-positive
+ * weight), LBM_EDEVICE. On error *out is NULL. */
 int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *state_a,
                void *state_b, void *work, void *stream, lbm_t *out);
 
@@ -127,8 +144,8 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *s
 int lbm_init(lbm_t h, const double *rho, const double *u);
 
 /* Advance nsteps >= 0 time steps (collide, force, partial bounce-back, stream,
- * halfway bounce-back: the discrete BGK update of Sec. 9.1 with the source of Sec. 7).
- * Async. */
+ * halfway bounce-back and free-slip walls: the discrete BGK update of Sec. 9.1 with
+ * the forcing of Sec. 7). Async. */
 int lbm_step(lbm_t h, int nsteps);
 
 /* One step from the state in `src` into `dst` (device state buffers of state_bytes,
@@ -165,7 +182,9 @@ int lbm_set_tau(lbm_t h, double tau);
  * lbm_adjoint_step are discarded. Async. */
 int lbm_adjoint_seed(lbm_t h, int axis, double norm, float *lam);
 
-/* One reverse step of the discrete adjoint of lbm_step (not in the paper).
+/* One reverse step of the discrete adjoint of lbm_step (not in the paper), for the
+ * source forcing and bounce-back walls: LBM_EUNSUPPORTED with LBM_FORCE_SHIFT or slip
+ * walls (as lbm_adjoint_seed).
  *   state   : the state buffer whose populations are pre-collision at step t (what the
  *             handle held before the forward step t -> t+1)
  *   lam_in  : dJ/df(t+1) (adjoint_bytes); lam_out: dJ/df(t) (distinct buffer)

@@ -142,6 +142,12 @@ int validate(const lbm_params *p, lbm_t h, Sizes *sz)
         return fail(h, LBM_EINVAL, "F16 storage: dev_scale_log2 must be in 0..40");
     if (p->stats == LBM_FERMI_DIRAC && (!(p->theta > 0) || !std::isfinite(p->theta) || !std::isfinite(p->mu)))
         return fail(h, LBM_EINVAL, "Fermi-Dirac weight needs finite theta > 0 and finite mu");
+    if (p->forcing != LBM_FORCE_SOURCE && p->forcing != LBM_FORCE_SHIFT)
+        return fail(h, LBM_EINVAL, "unknown forcing scheme %d", p->forcing);
+    if (p->slip & ~(LBM_SLIP_Y | LBM_SLIP_Z)) return fail(h, LBM_EINVAL, "slip: only LBM_SLIP_Y and LBM_SLIP_Z bits");
+    if (D == 2 && (p->slip & LBM_SLIP_Z)) return fail(h, LBM_EINVAL, "2D lattice: no z walls");
+    if (((p->slip & LBM_SLIP_Y) && p->ny < 3) || ((p->slip & LBM_SLIP_Z) && p->nz < 3))
+        return fail(h, LBM_EINVAL, "a free-slip axis needs at least 3 planes (2 walls and fluid)");
     if (sz) {
         sz->N = (int)N;
         sz->stride = (int)stride;
@@ -233,13 +239,24 @@ void fill_physics(lbm_t h)
         ph.oCp[s] = (float)(om * k.C[s] * k.cs * k.cs);
     }
     for (int i = 0; i < 3; ++i) ph.c1v[i] = (float)(k.A * h->p.E[i] / k.cs);
+    // velocity shift: j_eq - j = rho (shE + shB (U x B)) in stored lattice units
+    for (int i = 0; i < 3; ++i) ph.shE[i] = (float)((double)ph.scale * h->p.tau * k.cs * h->p.E[i]);
+    ph.shB = (float)((double)ph.scale * h->p.tau * k.cs * k.cs);
     ph.inv_cs2S = (float)(1.0 / (k.cs * k.cs) / (double)ph.scale);
 }
 
 bool has_B(const lbm_t h) { return h->p.B[0] != 0.0 || h->p.B[1] != 0.0 || h->p.B[2] != 0.0; }
 bool has_E(const lbm_t h) { return h->p.E[0] != 0.0 || h->p.E[1] != 0.0 || h->p.E[2] != 0.0; }
-int force_level(const lbm_t h) { return has_B(h) ? 2 : (has_E(h) ? 1 : 0); }
-const void *links_of(const lbm_t h) { return h->mask ? h->links : nullptr; }
+// kernel forcing variant: 0 none, 1 source with E, 2 source with E and B, 3 velocity shift
+int force_level(const lbm_t h)
+{
+    if (h->p.forcing == LBM_FORCE_SHIFT) return (has_E(h) || has_B(h)) ? 3 : 0;
+    return has_B(h) ? 2 : (has_E(h) ? 1 : 0);
+}
+// link masks exist where there are solids: obstacles of the mask, or slip wall planes
+bool has_solids(const lbm_t h) { return h->mask != nullptr || h->p.slip != 0; }
+const void *links_of(const lbm_t h) { return has_solids(h) ? h->links : nullptr; }
+bool adjoint_supported(const lbm_t h) { return h->p.forcing == LBM_FORCE_SOURCE && h->p.slip == 0; }
 
 double *work_out(lbm_t h) { return reinterpret_cast<double *>(h->work); }
 double *work_parts(lbm_t h) { return reinterpret_cast<double *>(h->work + work_layout(h->g.nblocks, h->stride).parts); }
@@ -356,9 +373,10 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *s
     h->g.div_ny = make_fastdiv(p->ny);
     h->g.mask = mask;
     h->g.s = s;
+    h->g.slip = p->slip;
     fill_physics(h);
     h->links = work_links(h);
-    if (mask) {
+    if (has_solids(h)) {
         const hipError_t e = launch_links(p->lattice, h->g, h->links, h->stream);
         if (e != hipSuccess) {
             delete h;
@@ -380,6 +398,7 @@ int lbm_init(lbm_t h, const double *rho, const double *u)
     a.ph = h->ph;
     a.rho = rho;
     a.u = u;
+    a.links = links_of(h);
     a.dst = h->buf[h->cur];
     const hipError_t e = launch_init(h->p.lattice, h->p.storage, a, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "init kernel launch");
@@ -396,7 +415,7 @@ int lbm_step(lbm_t h, int nsteps)
     a.g = h->g;
     a.ph = h->ph;
     a.links = links_of(h);
-    a.remap = use_xcd_remap(h->p.lattice, h->mask != nullptr, h->s != nullptr);
+    a.remap = use_xcd_remap(h->p.lattice, has_solids(h), h->s != nullptr);
     const int force = force_level(h);
     for (int t = 0; t < nsteps; ++t) {
         a.src = h->buf[h->cur];
@@ -416,7 +435,7 @@ int lbm_step_from(lbm_t h, const void *src, void *dst)
     a.g = h->g;
     a.ph = h->ph;
     a.links = links_of(h);
-    a.remap = use_xcd_remap(h->p.lattice, h->mask != nullptr, h->s != nullptr);
+    a.remap = use_xcd_remap(h->p.lattice, has_solids(h), h->s != nullptr);
     a.src = src;
     a.dst = dst;
     const hipError_t e = launch_step(h->p.lattice, h->p.storage, force_level(h), a, h->stream);
@@ -533,6 +552,8 @@ int lbm_adjoint_seed(lbm_t h, int axis, double norm, float *lam)
 {
     if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
     if (!lam) return fail(h, LBM_EINVAL, "lam is required");
+    if (!adjoint_supported(h))
+        return fail(h, LBM_EUNSUPPORTED, "the adjoint covers the source forcing and bounce-back walls only");
     if (axis < 0 || axis >= h->D) return fail(h, LBM_EINVAL, "axis must be in 0..D-1");
     if (!(norm != 0.0) || !std::isfinite(norm)) return fail(h, LBM_EINVAL, "norm must be finite and non-zero");
     const hipError_t e = launch_seed(h->p.lattice, h->g, (float)(1.0 / (h->k.cs * norm)), axis, lam, h->stream);
@@ -547,11 +568,13 @@ int lbm_adjoint_step(lbm_t h, const void *state, const float *lam_in, float *lam
     if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
     if (!state || !lam_in || !lam_out) return fail(h, LBM_EINVAL, "state, lam_in and lam_out are required");
     if (lam_in == lam_out) return fail(h, LBM_EINVAL, "lam_in and lam_out must be distinct buffers");
+    if (!adjoint_supported(h))
+        return fail(h, LBM_EUNSUPPORTED, "the adjoint covers the source forcing and bounce-back walls only");
     AdjointArgs a{};
     a.g = h->g;
     a.ph = h->ph;
     a.links = links_of(h);
-    a.remap = use_xcd_remap(h->p.lattice, h->mask != nullptr, h->s != nullptr);
+    a.remap = use_xcd_remap(h->p.lattice, has_solids(h), h->s != nullptr);
     a.state = state;
     a.lam_in = lam_in;
     a.lam_out = lam_out;

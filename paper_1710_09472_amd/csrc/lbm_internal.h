@@ -62,6 +62,7 @@ struct Geometry {
     int nblocks;      // tiles in the grid = ntx * ny * nz
     FastDiv div_ntx;  // division by ntx
     FastDiv div_ny;   // division by ny
+    int slip;         // free-slip wall planes (LBM_SLIP_Y | LBM_SLIP_Z)
     const uint8_t *mask;  // nullable
     const float *s;       // nullable
 };
@@ -95,6 +96,8 @@ struct Physics {
     float oCp[4];     // omega Cp_k
     float c1v[3];     // A E / c_s, so that c1q = e_q . c1v
     float inv_cs2S;   // inv_cs2 / scale
+    float shE[3];     // velocity shift: scale tau c_s E
+    float shB;        //   and scale tau c_s^2 (multiplies U x B)
 };
 
 struct StepArgs {
@@ -110,7 +113,8 @@ struct InitArgs {
     Geometry g;
     Physics ph;
     const double *rho;
-    const double *u;  // nullable
+    const double *u;     // nullable
+    const void *links;   // per-node link masks (nullable: no solids)
     void *dst;
 };
 

@@ -33,12 +33,12 @@ static int env_int(const char *name, int dflt)
 }
 
 // Nodes per thread of the step kernel (measured on MI355X): 1 for FP32 and for D3V19,
-// 2 for 16-bit D2V9; halved until it divides nx. LBM_STEP_VEC=1|2|4 overrides it.
+// 2 for 16-bit D2V9; halved until it divides nx. LBM_STEP_VEC=1|2 overrides it.
 int step_vector_width(int lattice, int storage, int nx)
 {
     static const int forced = env_int("LBM_STEP_VEC", 0);
     int v = forced;
-    if (v != 1 && v != 2 && v != 4) v = (storage != LBM_F32 && lattice == LBM_D2V9) ? 2 : 1;
+    if (v != 1 && v != 2) v = (storage != LBM_F32 && lattice == LBM_D2V9) ? 2 : 1;
     while (v > 1 && nx % v) v >>= 1;
     return v;
 }
@@ -276,13 +276,39 @@ __device__ __forceinline__ PullRows pull_rows(const Geometry &g, const Tile &t)
     return r;
 }
 
+// Index of e_q with its y (fy) and/or z (fz) component reversed.
+template <int LAT>
+constexpr int reflected(int q, bool fy, bool fz)
+{
+    using L = Lat<LAT>;
+    for (int b = 0; b < L::Q; ++b)
+        if (L::ex[b] == L::ex[q] && L::ey[b] == (fy ? -L::ey[q] : L::ey[q]) &&
+            L::ez[b] == (fz ? -L::ez[q] : L::ez[q]))
+            return b;
+    return -1;
+}
+
+// Element offset of the value pulled into the row of tile t as population q: slot q of
+// the row of x - e_q; where that row is a free-slip wall plane, the specular source,
+// i.e. slot qr (e_q with the wall-normal components reversed) of the row of x itself
+// (the tile's row is uniform over the block, so this choice is a scalar one).
 template <int LAT, int q>
 __device__ __forceinline__ size_t pull_row(const Geometry &g, const Tile &t, const PullRows &r)
 {
     using L = Lat<LAT>;
-    const int sy = L::ey[q] > 0 ? r.ym : (L::ey[q] < 0 ? r.yp : t.y);
-    const int sz = L::ez[q] > 0 ? r.zm : (L::ez[q] < 0 ? r.zp : t.z);
-    return (size_t)q * g.stride + (size_t)g.nx * (sy + g.ny * sz);
+    int sy = L::ey[q] > 0 ? r.ym : (L::ey[q] < 0 ? r.yp : t.y);
+    int sz = L::ez[q] > 0 ? r.zm : (L::ez[q] < 0 ? r.zp : t.z);
+    int p = q;
+    if (g.slip) {
+        const bool fy = L::ey[q] != 0 && (g.slip & LBM_SLIP_Y) && (sy == 0 || sy == g.ny - 1);
+        const bool fz = L::ez[q] != 0 && (g.slip & LBM_SLIP_Z) && (sz == 0 || sz == g.nz - 1);
+        if (fy) sy = t.y;
+        if (fz) sz = t.z;
+        constexpr int py = reflected<LAT>(q, true, false), pz = reflected<LAT>(q, false, true);
+        constexpr int pyz = reflected<LAT>(q, true, true);
+        p = fy ? (fz ? pyz : py) : (fz ? pz : q);
+    }
+    return (size_t)p * g.stride + (size_t)g.nx * (sy + g.ny * sz);
 }
 
 template <int LAT, int q, int V>
@@ -373,7 +399,8 @@ __device__ __forceinline__ void load_links(const typename LinkMask<LAT>::T *link
 //   sigma_q = (e.E / c_s)(A + 2 Bc e.U) + 2 C_k (c_s U.E + e.(B x U));
 //   d*_q = d_q + omega (deq_q - d_q) + rho what_k sigma_q;
 //   g_q = (1 - s) d*_q + s d_qbar.
-// FORCE: 0 no field, 1 E only, 2 E and B.
+// FORCE: 0 no field, 1 E only, 2 E and B (source term); 3 velocity shift (E and B): no
+// sigma, and deq_q taken at j + rho tau c_s (E + u x B), i.e. at u + tau (E + u x B).
 // ---------------------------------------------------------------------------------
 template <int LAT>
 struct Macro {
@@ -453,6 +480,17 @@ __device__ __forceinline__ void relax_node(const Physics &p, const float *D, flo
     const float rho = __builtin_fmaf(drho, p.inv_scale, p.rho0);
     const float kk = p.inv_cs2S * __builtin_amdgcn_rcpf(rho);
     float U[3] = {j[0] * kk, j[1] * kk, L::D == 3 ? j[2] * kk : 0.f};
+    if constexpr (FORCE == 3) {
+        // velocity shift: the equilibrium takes u + tau (E + u x B), i.e. j + rho (shE +
+        // shB U x B); the relaxation then moves momentum by rho (E + u x B) per step
+        const float W[3] = {U[1] * p.B[2] - U[2] * p.B[1], U[2] * p.B[0] - U[0] * p.B[2],
+                            U[0] * p.B[1] - U[1] * p.B[0]};  // U x B
+#pragma unroll
+        for (int i = 0; i < L::D; ++i) {
+            j[i] = __builtin_fmaf(rho, __builtin_fmaf(p.shB, W[i], p.shE[i]), j[i]);
+            U[i] = j[i] * kk;
+        }
+    }
     float U2 = U[0] * U[0] + U[1] * U[1];
     if constexpr (L::D == 3) U2 = __builtin_fmaf(U[2], U[2], U2);
     float wr[3], owd[3], P[3];
@@ -463,7 +501,7 @@ __device__ __forceinline__ void relax_node(const Physics &p, const float *D, flo
         P[k] = p.oCp[k] * U2;
     }
     float H[3][3];
-    if constexpr (FORCE >= 1) {
+    if constexpr (FORCE == 1 || FORCE == 2) {
         float UE = U[0] * p.E[0] + U[1] * p.E[1];
         if constexpr (L::D == 3) UE = __builtin_fmaf(U[2], p.E[2], UE);
         UE *= p.cs;
@@ -486,7 +524,7 @@ __device__ __forceinline__ void relax_node(const Physics &p, const float *D, flo
             const float eu = edot<LAT, q>(U);
             const float ej = edot<LAT, q>(j);
             float inner;
-            if constexpr (FORCE == 0)
+            if constexpr (FORCE == 0 || FORCE == 3)
                 inner = __builtin_fmaf(p.omBc * eu, eu, P[k]);
             else if constexpr (FORCE == 1)
                 inner = __builtin_fmaf(__builtin_fmaf(p.omBc, eu, p.c2q[q]), eu, P[k] + p.c1q[q]);
@@ -584,7 +622,10 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, int ntx, FastDiv di
 }
 
 // ---------------------------------------------------------------------------------
-// Link masks from the solid mask: bit q when x - e_q is solid, top bit when x is.
+// Link masks: the top bit when x is solid (an obstacle of the mask or a node of a
+// free-slip wall plane); bit q when the pull of population q into x bounces back, i.e.
+// its source x - e_q is an obstacle or, where x - e_q lies in a wall plane, the
+// specular source (x - e_q with the wall-axis coordinates of x) is an obstacle.
 // ---------------------------------------------------------------------------------
 template <int LAT>
 __global__ __launch_bounds__(kBlock) void k_links(Geometry g, typename LinkMask<LAT>::T *links)
@@ -596,23 +637,30 @@ __global__ __launch_bounds__(kBlock) void k_links(Geometry g, typename LinkMask<
     const int xm = wrapm(t.x0, g.nx), xp = wrapp(t.x0, g.nx);
     const int ym = wrapm(t.y, g.ny), yp = wrapp(t.y, g.ny);
     const int zm = wrapm(t.z, g.nz), zp = wrapp(t.z, g.nz);
-    LT bits = g.mask[t.own] ? LinkMask<LAT>::solid : (LT)0;
+    auto obstacle = [&](int x, int y, int z) { return g.mask && g.mask[x + g.nx * (y + g.ny * z)]; };
+    auto wall_y = [&](int y) { return (g.slip & LBM_SLIP_Y) && (y == 0 || y == g.ny - 1); };
+    auto wall_z = [&](int z) { return (g.slip & LBM_SLIP_Z) && (z == 0 || z == g.nz - 1); };
+    const bool own_solid = obstacle(t.x0, t.y, t.z) || wall_y(t.y) || wall_z(t.z);
+    LT bits = own_solid ? LinkMask<LAT>::solid : (LT)0;
 #pragma unroll
     for (int q = 1; q < L::Q; ++q) {
         const int sx = L::ex[q] > 0 ? xm : (L::ex[q] < 0 ? xp : t.x0);
-        const int sy = L::ey[q] > 0 ? ym : (L::ey[q] < 0 ? yp : t.y);
-        const int sz = L::ez[q] > 0 ? zm : (L::ez[q] < 0 ? zp : t.z);
-        if (g.mask[sx + g.nx * (sy + g.ny * sz)]) bits |= (LT)(1u << q);
+        int sy = L::ey[q] > 0 ? ym : (L::ey[q] < 0 ? yp : t.y);
+        int sz = L::ez[q] > 0 ? zm : (L::ez[q] < 0 ? zp : t.z);
+        if (L::ey[q] != 0 && wall_y(sy)) sy = t.y;
+        if (L::ez[q] != 0 && wall_z(sz)) sz = t.z;
+        if (obstacle(sx, sy, sz)) bits |= (LT)(1u << q);
     }
     links[t.own] = bits;
 }
 
 // ---------------------------------------------------------------------------------
-// K2: initial state. The stored state is post-collision and the next step pulls slot q
-// of node y into y + e_q, so node y holds in slot q the equilibrium deviation
-// f^eq_q(y + e_q) when y + e_q is fluid. A bounced value (y + e_q solid, pulled back into
-// y as population qbar) is f^eq_qbar(y): in slot q of y itself (own slot), or in slot
-// qbar of the solid node y + e_q (solid slot). Slots never read hold 0.
+// K2: initial state, written from the reader's side: every fluid node x stores its
+// equilibrium deviations f^eq_q(rho(x), u(x)) at the addresses its first pull reads
+// them from (the same pull_row as the step: slot q of x - e_q, or the specular source
+// beside a free-slip wall; for a bounce-back link slot qbar of x itself (own slot) or
+// slot q of the solid source (solid slot)). Every such address has exactly one reader,
+// so the writes do not overlap. Slots that no pull reads are left as they were.
 // ---------------------------------------------------------------------------------
 template <int LAT, int q>
 __device__ __forceinline__ float deq_moving(const Physics &p, float drho, float rho, const float *j,
@@ -629,58 +677,42 @@ __global__ __launch_bounds__(kBlock) void k_init(InitArgs a)
 {
     using L = Lat<LAT>;
     using T = typename Codec<ST>::T;
+    using LT = typename LinkMask<LAT>::T;
     const Geometry &g = a.g;
     const Physics &p = a.ph;
     const Tile t = tile_of(g, (int)blockIdx.x);
     if (!t.valid) return;
+    const LT lk = a.links ? static_cast<const LT *>(a.links)[t.own] : (LT)0;
+    if (lk & LinkMask<LAT>::solid) return;
     T *__restrict__ dst = static_cast<T *>(a.dst);
     const int N = g.nx * g.ny * g.nz;
-    const int xm = wrapm(t.x0, g.nx), xp = wrapp(t.x0, g.nx);
-    const int ym = wrapm(t.y, g.ny), yp = wrapp(t.y, g.ny);
-    const int zm = wrapm(t.z, g.nz), zp = wrapp(t.z, g.nz);
     const float inv_cs = p.cs * p.inv_cs2;
-    // rho, j, U of a node from the caller's FP64 fields (u in xi-units, j = rho c_s u)
-    auto node_state = [&](int m, float &drho, float &rho, float *j, float *U, float &U2) {
-        const double r = a.rho[m];
-        drho = (float)(r - (double)p.rho0);
-        rho = (float)r;
-        for (int i = 0; i < 3; ++i) {
-            const double ui = (a.u && i < L::D) ? a.u[(size_t)i * N + m] : 0.0;
-            U[i] = (float)ui * inv_cs;
-            j[i] = (float)(r * ui * (double)p.cs);
-        }
-        U2 = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
-    };
-    const bool own_solid = g.mask && g.mask[t.own];
-    float dev0 = 0.f, drho0 = 0.f, rho0 = 0.f, j0[3] = {0.f, 0.f, 0.f}, U0[3] = {0.f, 0.f, 0.f}, U20 = 0.f;
-    if (!own_solid) {
-        // rest population by closure, so that the deviations of the node sum to drho
-        node_state(t.own, drho0, rho0, j0, U0, U20);
-        float sum_eq = 0.f;
-        for_q<L::Q>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            if constexpr (q != 0) sum_eq += deq_moving<LAT, q>(p, drho0, rho0, j0, U0, U20);
-        });
-        dev0 = drho0 - sum_eq;
+    // rho, j, U of the node from the caller's FP64 fields (u in xi-units, j = rho c_s u)
+    const double r = a.rho[t.own];
+    const float drho = (float)(r - (double)p.rho0), rho = (float)r;
+    float j[3], U[3];
+    for (int i = 0; i < 3; ++i) {
+        const double ui = (a.u && i < L::D) ? a.u[(size_t)i * N + t.own] : 0.0;
+        U[i] = (float)ui * inv_cs;
+        j[i] = (float)(r * ui * (double)p.cs);
     }
-    dst[t.own] = Codec<ST>::enc(dev0, p.scale);
+    const float U2 = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+    // rest population by closure, so that the deviations of the node sum to drho
+    float sum_eq = 0.f;
+    for_q<L::Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        if constexpr (q != 0) sum_eq += deq_moving<LAT, q>(p, drho, rho, j, U, U2);
+    });
+    dst[t.own] = Codec<ST>::enc(drho - sum_eq, p.scale);
+    const PullRows rows = pull_rows<1>(g, t);
     for_q<L::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         if constexpr (q != 0) {
-            const int tx = L::ex[q] > 0 ? xp : (L::ex[q] < 0 ? xm : t.x0);
-            const int ty = L::ey[q] > 0 ? yp : (L::ey[q] < 0 ? ym : t.y);
-            const int tz = L::ez[q] > 0 ? zp : (L::ez[q] < 0 ? zm : t.z);
-            const int tn = tx + g.nx * (ty + g.ny * tz);
-            float dev = 0.f;
-            const bool tn_solid = g.mask && g.mask[tn];
-            if (!tn_solid && (kSolidSlotBB<ST> || !own_solid)) {
-                float dr, r, j[3], U[3], U2;
-                node_state(tn, dr, r, j, U, U2);
-                dev = deq_moving<LAT, q>(p, dr, r, j, U, U2);
-            } else if (tn_solid && !kSolidSlotBB<ST> && !own_solid) {
-                dev = deq_moving<LAT, L::opp[q]>(p, drho0, rho0, j0, U0, U20);  // bounced, own slot
-            }
-            dst[q * g.stride + t.own] = Codec<ST>::enc(dev, p.scale);
+            const T v = Codec<ST>::enc(deq_moving<LAT, q>(p, drho, rho, j, U, U2), p.scale);
+            if (!kSolidSlotBB<ST> && ((lk >> q) & 1u))
+                dst[(size_t)L::opp[q] * g.stride + t.own] = v;  // bounced, own slot
+            else
+                *at32(dst + pull_row<LAT, q>(g, t, rows), pull_x<LAT, q, 1>(rows, 0)) = v;
         }
     });
 }
@@ -1048,8 +1080,10 @@ hipError_t step_v(int force, const StepArgs &a, hipStream_t st)
         LBM_STEP(M, S, 0); \
     else if (force == 1)   \
         LBM_STEP(M, S, 1); \
+    else if (force == 2)   \
+        LBM_STEP(M, S, 2); \
     else                   \
-        LBM_STEP(M, S, 2)
+        LBM_STEP(M, S, 3)
     if (mask) {
         if (soft) LBM_STEP_F(true, true); else LBM_STEP_F(true, false);
     } else {
@@ -1064,7 +1098,6 @@ template <int LAT, int ST>
 hipError_t step_lat_st(int force, const StepArgs &a, hipStream_t st)
 {
     const int v = step_vector_width(LAT, ST, a.g.nx);
-    if (v == 4) return step_v<LAT, ST, 4>(force, a, st);
     if (v == 2) return step_v<LAT, ST, 2>(force, a, st);
     return step_v<LAT, ST, 1>(force, a, st);
 }

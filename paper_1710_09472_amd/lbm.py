@@ -17,6 +17,8 @@ LIB_PATH = PKG / "liblbm_hip.so"
 LATTICES = {"D2V9": 0, "D3V19": 1, "D3V15": 2}
 STATS = {"fd": 0, "hermite": 2}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+FORCING = {"source": 0, "shift": 1}
+SLIP_Y, SLIP_Z = 1, 2
 
 LBM_OK, LBM_EINVAL, LBM_EUNSUPPORTED, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 
@@ -35,7 +37,7 @@ class LbmParams(ctypes.Structure):
         ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
         ("theta", ctypes.c_double), ("mu", ctypes.c_double), ("tau", ctypes.c_double),
         ("E", ctypes.c_double * 3), ("B", ctypes.c_double * 3), ("rho0", ctypes.c_double),
-        ("dev_scale_log2", ctypes.c_int),
+        ("dev_scale_log2", ctypes.c_int), ("forcing", ctypes.c_int), ("slip", ctypes.c_int),
     ]
 
 
@@ -106,7 +108,10 @@ def _check(rc, handle=None):
 
 
 def make_params(lattice="D2V9", nx=1, ny=1, nz=1, tau=0.8, E=(0.0, 0.0, 0.0), B=(0.0, 0.0, 0.0),
-                storage="f32", dev_scale_log2=0, rho0=1.0, stats="fd", theta=1.0 / 270.0, mu=1.0) -> LbmParams:
+                storage="f32", dev_scale_log2=0, rho0=1.0, stats="fd", theta=1.0 / 270.0, mu=1.0,
+                forcing="source", slip=0) -> LbmParams:
+    """forcing: "source" (xi-dependent source term) or "shift" (velocity shift);
+    slip: free-slip wall planes, SLIP_Y | SLIP_Z."""
     p = LbmParams()
     p.lattice = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
     p.stats = STATS[stats] if isinstance(stats, str) else int(stats)
@@ -117,6 +122,8 @@ def make_params(lattice="D2V9", nx=1, ny=1, nz=1, tau=0.8, E=(0.0, 0.0, 0.0), B=
     p.B = (ctypes.c_double * 3)(*[float(v) for v in B])
     p.rho0 = float(rho0)
     p.dev_scale_log2 = int(dev_scale_log2)
+    p.forcing = FORCING[forcing] if isinstance(forcing, str) else int(forcing)
+    p.slip = int(slip)
     return p
 
 
@@ -163,13 +170,14 @@ class Simulation:
 
     def __init__(self, lattice="D2V9", nx=1, ny=1, nz=1, tau=0.8, E=(0.0, 0.0, 0.0), B=(0.0, 0.0, 0.0),
                  storage="f32", dev_scale_log2=0, rho0=1.0, stats="fd", theta=1.0 / 270.0, mu=1.0,
-                 mask=None, s=None, device="cuda"):
+                 mask=None, s=None, device="cuda", forcing="source", slip=0):
         import torch
 
         self.torch = torch
         self.lib = load_library()
         self.lattice = lattice
-        self.params = make_params(lattice, nx, ny, nz, tau, E, B, storage, dev_scale_log2, rho0, stats, theta, mu)
+        self.params = make_params(lattice, nx, ny, nz, tau, E, B, storage, dev_scale_log2, rho0, stats, theta, mu,
+                                  forcing, slip)
         self.sizes = buffer_sizes(self.params)
         self.Q, self.D, self.e = lattice_info(lattice)
         self.N = nx * ny * nz

@@ -21,6 +21,18 @@ Workloads (all sizes in lattice nodes):
   (the Ohm's-law test of Sec. 9.4 at a larger size).
 * ``soft_porous_3d``  D3V19 128^3 periodic with a soft partial-bounce-back field s in
   [0, 1] of mean 0.2 (seed 3), E = (1e-6, 0, 0), tau = 0.75, 600 steps.
+
+The paper's own setups (Sec. 9.3, 9.4), with its velocity-shift forcing:
+
+* ``ohm_paper_2d``  D2V9 512x256, free-slip walls y = 0, 255, periodic x, 64
+  non-overlapping disks of radius 3 (seed 4, porosity 0.986), E_x = 1e-7, tau = 0.9.
+* ``ohm_paper_3d``  D3V19 128^3, free-slip walls y and z, periodic x, 450 non-overlapping
+  balls of radius 3 (seed 5, porosity 0.974), E_x = 1e-7, tau = 0.9.
+* ``poiseuille_paper_2d``  D2V9 256x256, bounce-back rows y = 0, 255, periodic x,
+  E_x = 1e-8, tau given (the paper sweeps five values), 10^6 steps.
+
+These use density 1 where the paper starts from mu = 1 (rho = I_0): the update is
+homogeneous of degree one in f, so the velocity field does not depend on that scale.
 """
 from __future__ import annotations
 
@@ -45,6 +57,8 @@ class Workload:
     mask: np.ndarray | None = None    # (N,) uint8, 1 = solid, or None
     s: np.ndarray | None = None       # (N,) float64 in [0, 1], or None
     notes: dict = field(default_factory=dict)
+    forcing: str = "source"           # "source" (xi-dependent term) or "shift" (velocity shift)
+    slip: int = 0                     # free-slip wall planes: 1 y, 2 z (bits)
 
     @property
     def N(self) -> int:
@@ -136,6 +150,51 @@ def disk_mask_2d(nx: int, ny: int, radius: int, solid_fraction: float, seed: int
     return solid.reshape(-1).astype(np.uint8), len(centres)
 
 
+def ball_obstacles(dims: tuple, radius: int, count: int, seed: int, margin_axes: tuple = (),
+                   max_tries: int = 1_000_000) -> np.ndarray:
+    """`count` non-overlapping discrete balls (disks in 2D) of `radius` on the grid
+    dims = (nx, ny, nz), periodic along every axis not in `margin_axes`.
+
+    Random sequential addition (numpy default_rng(seed)): integer centres drawn
+    uniformly, along each axis in `margin_axes` (1 = y, 2 = z) restricted to
+    [radius + 1, n - 2 - radius] so that no ball touches the boundary planes; a centre
+    is accepted if its periodic distance to every accepted centre is at least
+    2 radius + 1. A node is solid if its (periodic) squared distance to a centre is at
+    most radius^2. Returns the uint8 mask (1 = solid).
+    """
+    nx, ny, nz = dims
+    n = np.array([nx, ny, nz])
+    rng = np.random.default_rng(seed)
+    r = int(radius)
+    d3 = 3 if nz > 1 else 2
+    off = np.stack(np.meshgrid(*[np.arange(-r, r + 1)] * d3, indexing="ij"), -1).reshape(-1, d3)
+    off = off[(off ** 2).sum(1) <= r * r]
+    if d3 == 2:
+        off = np.concatenate([off, np.zeros((len(off), 1), int)], 1)
+    lo = np.zeros(3, int)
+    hi = n.copy()
+    for a in margin_axes:
+        lo[a], hi[a] = r + 1, n[a] - 1 - r
+    centres = []
+    tries = 0
+    while len(centres) < count:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("ball placement did not fit the requested count")
+        c = np.array([rng.integers(lo[i], hi[i]) if n[i] > 1 else 0 for i in range(3)])
+        if centres:
+            dd = np.abs(np.array(centres) - c)
+            dd = np.minimum(dd, n - dd)
+            if ((dd ** 2).sum(1) < (2 * r + 1) ** 2).any():
+                continue
+        centres.append(c)
+    solid = np.zeros((nz, ny, nx), dtype=np.uint8)
+    for c in centres:
+        p = (c + off) % n
+        solid[p[:, 2], p[:, 1], p[:, 0]] = 1
+    return solid.reshape(-1)
+
+
 def soft_porosity_3d(n: int, mean: float, seed: int, sigma: float = 3.0) -> np.ndarray:
     """Soft solid fraction s in [0, 1] on a periodic n^3 grid.
 
@@ -201,6 +260,25 @@ def soft_porous_3d(n: int = 128, seed: int = 3, mean: float = 0.2) -> Workload:
     s = soft_porosity_3d(n, mean, seed)
     return Workload("soft_porous_3d", "D3V19", n, n, n, tau=0.75, steps=600, E=(1e-6, 0.0, 0.0),
                     rho=np.ones(n ** 3), s=s)
+
+
+def ohm_paper_2d(Ex: float = 1e-7, seed: int = 4, steps: int = 20000) -> Workload:
+    nx, ny = 512, 256
+    mask = ball_obstacles((nx, ny, 1), 3, 64, seed, margin_axes=(1,))
+    return Workload("ohm_paper_2d", "D2V9", nx, ny, 1, tau=0.9, steps=steps, E=(Ex, 0.0, 0.0),
+                    rho=np.ones(nx * ny), mask=mask, forcing="shift", slip=1)
+
+
+def ohm_paper_3d(Ex: float = 1e-7, seed: int = 5, steps: int = 20000) -> Workload:
+    n = 128
+    mask = ball_obstacles((n, n, n), 3, 450, seed, margin_axes=(1, 2))
+    return Workload("ohm_paper_3d", "D3V19", n, n, n, tau=0.9, steps=steps, E=(Ex, 0.0, 0.0),
+                    rho=np.ones(n ** 3), mask=mask, forcing="shift", slip=3)
+
+
+def poiseuille_paper_2d(tau: float = 0.8, n: int = 256, steps: int = 1_000_000) -> Workload:
+    return Workload("poiseuille_paper_2d", "D2V9", n, n, 1, tau=tau, steps=steps, E=(1e-8, 0.0, 0.0),
+                    rho=np.ones(n * n), mask=channel_mask_2d(n, n), forcing="shift")
 
 
 def random_fields(lattice: str, nx: int, ny: int, nz: int = 1, seed: int = 0, drho: float = 0.05,

@@ -19,7 +19,7 @@ def gpu_sim(wl: W.Workload, storage="f32", dev_scale_log2=0, E=None, B=None):
 
     sim = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E if E is None else E,
                      B=wl.B if B is None else B, storage=storage, dev_scale_log2=dev_scale_log2,
-                     mask=wl.mask, s=wl.s)
+                     mask=wl.mask, s=wl.s, forcing=wl.forcing, slip=wl.slip)
     sim.init(wl.rho, wl.u)
     return sim
 
@@ -34,7 +34,8 @@ def gpu_fields(sim):
 
 def oracle_model(wl: W.Workload, nx=None, ny=None, nz=None, E=None, B=None):
     return OracleModel(wl.lattice, nx or wl.nx, ny or wl.ny, nz or wl.nz, tau=wl.tau,
-                       E=wl.E if E is None else E, B=wl.B if B is None else B)
+                       E=wl.E if E is None else E, B=wl.B if B is None else B, forcing=wl.forcing,
+                       slip=wl.slip)
 
 
 def oracle_fields(wl: W.Workload, steps: int):

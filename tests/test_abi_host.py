@@ -140,3 +140,20 @@ def test_buffer_sizes():
     # adjoint partials (4 doubles per 64-node wave)
     nwaves = 2 * 7 * 4  # ceil(300 / 256) 256-node tiles per row, 4 waves each
     assert s16["work"] >= 4 * st + 8 * 1024 * 5 + 32 * nwaves
+
+def test_scheme_validation():
+    """Forcing and free-slip parameters are validated on the host (no device work)."""
+    lib = lbm.load_library()
+    sizes = ctypes.c_size_t()
+    bad = [
+        lbm.make_params("D2V9", 16, 8, forcing=2),
+        lbm.make_params("D2V9", 16, 8, slip=lbm.SLIP_Z),          # no z walls in 2D
+        lbm.make_params("D2V9", 16, 8, slip=4),                    # unknown bit
+        lbm.make_params("D2V9", 16, 2, slip=lbm.SLIP_Y),           # walls leave no fluid row
+        lbm.make_params("D3V19", 8, 8, 2, slip=lbm.SLIP_Z),
+    ]
+    for p in bad:
+        assert lib.lbm_buffer_sizes(ctypes.byref(p), ctypes.byref(sizes), None, None, None) == lbm.LBM_EINVAL
+    for p in (lbm.make_params("D2V9", 16, 3, forcing="shift", slip=lbm.SLIP_Y),
+              lbm.make_params("D3V19", 8, 3, 3, forcing="shift", slip=lbm.SLIP_Y | lbm.SLIP_Z)):
+        assert lib.lbm_buffer_sizes(ctypes.byref(p), ctypes.byref(sizes), None, None, None) == lbm.LBM_OK
