@@ -38,7 +38,8 @@ PROFILE_DIR = ROOT / "profiles"
 
 
 # dev_scale_log2 of the FP16 runs: max|deviation| x 2^k near 2^12 for each workload
-F16_SCALE = {"throughput_2d": 12, "hall_duct_3d": 28, "porous_ohm_2d": 25, "soft_porous_3d": 28}
+F16_SCALE = {"throughput_2d": 12, "hall_duct_3d": 28, "porous_ohm_2d": 25, "soft_porous_3d": 28,
+             "ohm_paper_2d": 30, "ohm_paper_3d": 30, "poiseuille_paper_2d": 30}
 
 
 WORKLOAD_DESC = {
@@ -50,6 +51,12 @@ WORKLOAD_DESC = {
                      "E_x=1e-7, tau=0.9",
     "soft_porous_3d": "soft_porous_3d: D3V19 128^3 periodic, partial bounce-back field s of mean 0.2 (seed 3), "
                       "E_x=1e-6, tau=0.75",
+    "ohm_paper_2d": "ohm_paper_2d: D2V9 512x256, free-slip walls y, 64 disks r=3 (seed 4, porosity 0.986), "
+                    "velocity-shift forcing E_x=1e-7, tau=0.9",
+    "ohm_paper_3d": "ohm_paper_3d: D3V19 128^3, free-slip walls y and z, 450 balls r=3 (seed 5, porosity 0.974), "
+                    "velocity-shift forcing E_x=1e-7, tau=0.9",
+    "poiseuille_paper_2d": "poiseuille_paper_2d: D2V9 256x256, bounce-back rows y=0,255, velocity-shift forcing "
+                           "E_x=1e-8, tau=0.8",
 }
 
 
@@ -57,7 +64,9 @@ def make_workload(name: str):
     from paper_1710_09472_amd import workloads as W
 
     return {"throughput_2d": W.throughput_2d, "hall_duct_3d": W.hall_duct_3d,
-            "porous_ohm_2d": W.porous_ohm_2d, "soft_porous_3d": W.soft_porous_3d}[name]()
+            "porous_ohm_2d": W.porous_ohm_2d, "soft_porous_3d": W.soft_porous_3d,
+            "ohm_paper_2d": W.ohm_paper_2d, "ohm_paper_3d": W.ohm_paper_3d,
+            "poiseuille_paper_2d": W.poiseuille_paper_2d}[name]()
 
 
 def bytes_per_node(Q: int, elem: int) -> int:
@@ -65,13 +74,29 @@ def bytes_per_node(Q: int, elem: int) -> int:
     return 2 * Q * elem
 
 
+def solid_nodes(wl):
+    """Solid flags of a workload: its obstacles and its free-slip wall planes (or None)."""
+    import numpy as np
+
+    if wl.mask is None and not wl.slip:
+        return None
+    solid = np.zeros((wl.nz, wl.ny, wl.nx), np.uint8) if wl.mask is None else \
+        wl.mask.reshape(wl.nz, wl.ny, wl.nx).copy()
+    if wl.slip & 1:
+        solid[:, [0, wl.ny - 1], :] = 1
+    if wl.slip & 2:
+        solid[[0, wl.nz - 1], :, :] = 1
+    return solid.reshape(-1)
+
+
 def algorithmic_bytes(wl, Q: int, elem: int) -> int:
     """Minimum HBM bytes of one step: the populations of every fluid node read and
     written once, plus one byte of solid flag per node where there are solids and the
     FP32 porosity field where there is one."""
-    fluid = wl.N if wl.mask is None else int((wl.mask == 0).sum())
+    solid = solid_nodes(wl)
+    fluid = wl.N if solid is None else int((solid == 0).sum())
     b = fluid * bytes_per_node(Q, elem)
-    if wl.mask is not None:
+    if solid is not None:
         b += wl.N
     if wl.s is not None:
         b += 4 * wl.N
@@ -183,7 +208,7 @@ def cpu_baseline(wl, target_s: float = 12.0):
     ny = min(wl.ny, 256) if wl.nz == 1 else wl.ny
     n = wl.nx * ny * nz
     cut = lambda a: None if a is None else a.reshape(wl.nz, wl.ny, wl.nx)[:nz, :ny].reshape(-1)
-    m = OracleModel(wl.lattice, wl.nx, ny, nz, tau=wl.tau, E=wl.E, B=wl.B)
+    m = OracleModel(wl.lattice, wl.nx, ny, nz, tau=wl.tau, E=wl.E, B=wl.B, forcing=wl.forcing, slip=wl.slip)
     mask, s = cut(wl.mask), cut(wl.s)
     f = m.init_state(cut(wl.rho), mask=mask)
     f = m.run(f, 1, mask=mask, s=s)  # first call: thread start-up and page faults, not timed
@@ -237,7 +262,7 @@ def main():
     elem = 4 if st == "f32" else 2
     k16 = F16_SCALE[args.workload] if st == "f16" else 0
     sim = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E, B=wl.B, storage=st,
-                     dev_scale_log2=k16, mask=wl.mask, s=wl.s)
+                     dev_scale_log2=k16, mask=wl.mask, s=wl.s, forcing=wl.forcing, slip=wl.slip)
     sim.init(wl.rho, wl.u)
     wall, ev = timed_steps(sim, args.steps, args.warmup)
     t_launch = ev / args.steps
@@ -270,7 +295,8 @@ def main():
                              "checkpointed_128cube": adjoint_pipeline()}
 
     kernel = f"k_step<{wl.lattice},{st.upper()}" + (",mask" if wl.mask is not None else "") + \
-        (",soft" if wl.s is not None else "") + ">"
+        (",slip" if wl.slip else "") + (",soft" if wl.s is not None else "") + \
+        (",shift" if wl.forcing == "shift" else "") + ">"
     desc = WORKLOAD_DESC[args.workload] + {"f32": ", FP32", "f16": f", FP16 x 2^{k16}", "bf16": ", BF16"}[st] + \
         " deviation storage"
     out = {
@@ -292,8 +318,9 @@ def main():
                      "kernel": kernel, "bytes_per_launch": alg,
                      "avg_launch_ms": round(t_launch * 1e3, 5)},
     }
-    if wl.mask is not None:
-        out["fluid_MLUPS"] = round(int((wl.mask == 0).sum()) * args.steps / wall / 1e6, 1)
+    solid = solid_nodes(wl)
+    if solid is not None:
+        out["fluid_MLUPS"] = round(int((solid == 0).sum()) * args.steps / wall / 1e6, 1)
     if default:
         out["storage16"] = extras.get("f16") and {"f16": extras["f16"], "bf16": extras["bf16"]}
         out["adjoint"] = extras.get("adjoint")

@@ -564,6 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, int ntx, FastDiv di
     using LT = typename LinkMask<LAT>::T;
     const int bid = a.remap ? xcd_remap((int)blockIdx.x, nblocks) : (int)blockIdx.x;
     const Tile t = tile_of<V>(a.g, bid, ntx, div_ntx);
+    if (!t.valid) return;  // beyond the row (rows shorter than a block): no work
     LT lk[V];
     if (MASK) {
         load_links<LAT, V>(static_cast<const LT *>(a.links), t.own, lk);
@@ -579,7 +580,6 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, int ntx, FastDiv di
     float o[V][L::Q];
 #pragma unroll
     for (int i = 0; i < V; ++i) collide<LAT, SOFT, FORCE>(a.ph, d[i], SOFT ? sv[i] : 0.f, o[i]);
-    if (!t.valid) return;
     bool fluid[V];
     bool all_fluid = true;
     LT links = 0;  // union of the solid-neighbour bits of the fluid nodes
@@ -900,6 +900,13 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
     const bool last_lane = (threadIdx.x & 63) == 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     double *part = a.partials + ((size_t)blockIdx.x * (kBlock / 64) + wave) * 4;
+    // whole waves beyond the row (rows shorter than a block) have no work beyond a zero
+    // partial; partial waves go on with their extra lanes idle (the sums need 64 lanes)
+    if ((bid - fast_div(bid, g.div_ntx) * g.ntx) * kBlock + wave * 64 >= g.nx) {
+        if (!a.accumulate && last_lane)
+            for (int c = 0; c < 4; ++c) part[c] = 0.0;
+        return;
+    }
     double prev[4] = {0.0, 0.0, 0.0, 0.0};
     if (a.accumulate)
         for (int c = 0; c < 4; ++c) prev[c] = part[c];

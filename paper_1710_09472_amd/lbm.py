@@ -170,7 +170,7 @@ class Simulation:
 
     def __init__(self, lattice="D2V9", nx=1, ny=1, nz=1, tau=0.8, E=(0.0, 0.0, 0.0), B=(0.0, 0.0, 0.0),
                  storage="f32", dev_scale_log2=0, rho0=1.0, stats="fd", theta=1.0 / 270.0, mu=1.0,
-                 mask=None, s=None, device="cuda", forcing="source", slip=0):
+                 mask=None, s=None, device="cuda", forcing="source", slip=0, work=None):
         import torch
 
         self.torch = torch
@@ -189,7 +189,10 @@ class Simulation:
             if arr is not None and arr.numel() != self.N:
                 raise ValueError(f"{name} must have {self.N} entries")
         self.bufs = [torch.zeros(self.sizes["state"], dtype=torch.uint8, device=self.device) for _ in range(2)]
-        self.work = torch.zeros(self.sizes["work"], dtype=torch.uint8, device=self.device)
+        # workspace: the caller's (uint8 tensor of at least work bytes, any content) or zeros
+        self.work = torch.zeros(self.sizes["work"], dtype=torch.uint8, device=self.device) if work is None else work
+        if self.work.numel() < self.sizes["work"]:
+            raise ValueError(f"work must hold {self.sizes['work']} bytes")
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         _check(self.lib.lbm_create(ctypes.byref(self.params), _ptr(self.mask), _ptr(self.s), _ptr(self.bufs[0]),

@@ -7,6 +7,7 @@ import pytest
 import torch
 
 from oracle.oracle import OracleModel
+from paper_1710_09472_amd import lbm
 from paper_1710_09472_amd import workloads as W
 from paper_1710_09472_amd.adjoint import Problem, mean_current
 from parity_helpers import gpu_sim, permutation_to_oracle
@@ -107,6 +108,39 @@ def test_held_partials_match_per_step_reduction():
     assert torch.equal(lam_each, lam_held)
     np.testing.assert_allclose(g_held, g_each, rtol=1e-12, atol=1e-15 * np.abs(g_each).max())
     np.testing.assert_allclose(g_spoil, g_held, rtol=1e-12, atol=1e-15 * np.abs(g_each).max())
+
+
+def test_workspace_content_does_not_matter():
+    """The workspace is caller memory with no required content: a handle whose work
+    buffer starts as 0xFF bytes (NaN doubles) gives the same adjoint gradients. The grid
+    has a 260-node row (a block with three idle waves per row)."""
+    wl = _wl(CASES[1])
+    T = 5
+
+    def grads(work):
+        sim = lbm.Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E, B=wl.B, mask=wl.mask,
+                             s=wl.s, work=work)
+        sim.init(wl.rho, wl.u)
+        states = [sim.get_state()]
+        for _ in range(T):
+            sim.step(1)
+            states.append(sim.get_state())
+        lam = [sim.adjoint_seed(0, wl.N), sim.new_adjoint()]
+        gs = torch.zeros(wl.N, dtype=torch.float32, device="cuda")
+        gsc = torch.zeros(4, dtype=torch.float64, device="cuda")
+        cur = 0
+        for t in range(T - 1, -1, -1):
+            sim.adjoint_step(states[t], lam[cur], lam[cur ^ 1], gs, gsc if t == 0 else None)
+            cur ^= 1
+        torch.cuda.synchronize()
+        return gsc.cpu().numpy(), gs.cpu().numpy()
+
+    size = lbm.buffer_sizes(lbm.make_params(wl.lattice, wl.nx, wl.ny, wl.nz))["work"]
+    g0, s0 = grads(None)
+    g1, s1 = grads(torch.full((size,), 255, dtype=torch.uint8, device="cuda"))
+    assert np.isfinite(g1).all()
+    np.testing.assert_array_equal(g1, g0)
+    np.testing.assert_array_equal(s1, s0)
 
 
 def test_autograd_checkpointed_vs_oracle_fd():
