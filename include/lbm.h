@@ -41,9 +41,12 @@ typedef struct lbm_s *lbm_t;
 enum { LBM_D2V9 = 0, LBM_D3V19 = 1, LBM_D3V15 = 2 };
 
 /* Weight functions: the Fermi-Dirac electron weight 1/(exp((xi^2 - mu)/theta) + 1) of
- * eq. (weight-func-isotherm-eq), Sec. 9.1, or the Hermite weight of eq.
- * (hermite-weight-eq), Sec. 2 (theta and mu ignored), which yields textbook D2Q9/D3Q19. */
-enum { LBM_FERMI_DIRAC = 0, LBM_HERMITE = 2 };
+ * eq. (weight-func-isotherm-eq), Sec. 9.1; the Bose-Einstein weight
+ * 1/(exp((xi^2 - mu)/theta) - 1), the other semiclassical form of eq. (be-fd-dist-eq),
+ * Sec. 2 (needs mu < 0, fugacity z = e^(mu/theta) < 1; the paper gives no parameters);
+ * or the Hermite weight of eq. (hermite-weight-eq), Sec. 2 (theta and mu ignored),
+ * which yields textbook D2Q9/D3Q19. */
+enum { LBM_FERMI_DIRAC = 0, LBM_BOSE_EINSTEIN = 1, LBM_HERMITE = 2 };
 
 /* Population storage. All arithmetic is FP32; storage holds deviations
  * d_a = f_a - what_a rho0 from the rest equilibrium (what_a = w_a / I_0):

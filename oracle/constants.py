@@ -10,7 +10,11 @@ and returned as Python floats (or mpf when asked), directly from the paper's
 definitions:
 
 * weight functions: Fermi-Dirac electron weight, eq. (weight-func-isotherm-eq) of
-  Sec. 9.1; Hermite weight, eq. (hermite-weight-eq) of Sec. 2;
+  Sec. 9.1; the Bose-Einstein weight of the same form, eq. (be-fd-dist-eq) of Sec. 2
+  with u = 0 and the xi^2/theta scaling of Sec. 9.1; Hermite weight,
+  eq. (hermite-weight-eq) of Sec. 2;
+* density from chemical potential, rho = I_0(theta, mu), and its inverse by root
+  finding (Sec. 9.1-9.2: rho = (pi theta)^(D/2) g_(D/2)(e^(mu/theta)));
 * weight integrals I_2N: eq. (i2n-cont2) of Sec. 3 (radial form);
 * polynomial coefficients c_K, c'_K, cbar_K, Delta_2K, J_2K: the coefficient list
   of Sec. 3 (K <= 2 only; the second-order model of Sec. 9 needs nothing higher);
@@ -38,12 +42,17 @@ def _omega(stats: str, theta, mu, D: int):
 
     * "fd": eq. (weight-func-isotherm-eq), Sec. 9.1: 1 / (exp((xi^2 - mu)/theta) + 1);
       with theta = 1/270, mu = 1 this is 1/(e^-270 e^(270 xi^2) + 1).
+    * "be": the Bose-Einstein form, 1 / (exp((xi^2 - mu)/theta) - 1), mu < 0 (z < 1).
     * "hermite": eq. (hermite-weight-eq), Sec. 2: (2 pi)^(-D/2) exp(-xi^2/2).
     """
     theta = mp.mpf(theta)
     mu = mp.mpf(mu)
     if stats == "fd":
         return lambda x: 1 / (mp.exp((x * x - mu) / theta) + 1)
+    if stats == "be":
+        if mu >= 0:
+            raise ValueError("the Bose-Einstein weight needs mu < 0")
+        return lambda x: 1 / mp.expm1((x * x - mu) / theta)
     if stats == "hermite":
         pref = (2 * mp.pi) ** (-mp.mpf(D) / 2)
         return lambda x: pref * mp.exp(-x * x / 2)
@@ -82,6 +91,12 @@ def weight_integral(D: int, twoN: int, stats: str = "fd", theta="1/270", mu=1.0)
     f = lambda x: w(x) * x ** (2 * N + D - 1)
     if stats == "fd":
         pts = _fermi_edge_points(th, mu)
+        val = mp.quad(f, pts) + mp.quad(f, [pts[-1], mp.inf])
+    elif stats == "be":
+        # the BE weight varies on the scales sqrt(|mu|) (near 0) and sqrt(theta)
+        sc = sorted({mp.sqrt(abs(mp.mpf(mu))), mp.sqrt(th)})
+        pts = [mp.mpf(0)] + [c * k for c in sc for k in (mp.mpf(1) / 4, 1, 4)] + [mp.sqrt(th) * 16]
+        pts = sorted(set(pts))
         val = mp.quad(f, pts) + mp.quad(f, [pts[-1], mp.inf])
     else:
         val = mp.quad(f, [0, 1, 3, 6, 12, mp.inf])
@@ -173,3 +188,26 @@ def lattice_vectors(lattice: str):
             if sum(c * c for c in v) == n2:
                 vecs.append(tuple(v))
     return vecs
+
+
+def density_from_mu(D: int, stats: str = "fd", theta="1/270", mu=1.0) -> mp.mpf:
+    """rho(mu) at fixed theta: the zeroth weight integral, rho = I_0 (Sec. 9.1, the
+    relation rho = (pi theta)^(D/2) g_(D/2)(e^(mu/theta)) that sets initial conditions)."""
+    return weight_integral(D, 0, stats, theta, mu)
+
+
+def mu_from_density(D: int, rho, stats: str = "fd", theta="1/270") -> mp.mpf:
+    """The inverse of density_from_mu by secant iteration on mu (rho is increasing in
+    mu). Starting points: the degenerate estimate (D rho Gamma(D/2) / (2 pi^(D/2)))^(2/D)
+    for FD (Sommerfeld's leading term) and theta ln(rho / (pi theta)^(D/2)) (the
+    Boltzmann limit) for BE."""
+    th = mp.mpf(1) / 270 if theta == "1/270" else mp.mpf(theta)
+    rho = mp.mpf(rho)
+    if stats == "fd":
+        x0 = (D * rho * mp.gamma(mp.mpf(D) / 2) / (2 * mp.pi ** (mp.mpf(D) / 2))) ** (mp.mpf(2) / D)
+        x0 = max(x0, th)
+    else:
+        x0 = min(th * mp.log(rho / (mp.pi * th) ** (mp.mpf(D) / 2)), -th / 10)
+    g = lambda m: weight_integral(D, 0, stats, th, m) - rho
+    return mp.findroot(g, (x0, x0 * (1 + mp.mpf(1) / 1000) if x0 != 0 else th / 1000), solver="secant",
+                       tol=mp.mpf(10) ** (-30))

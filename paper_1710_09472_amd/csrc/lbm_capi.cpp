@@ -123,7 +123,7 @@ int validate(const lbm_params *p, lbm_t h, Sizes *sz)
     if (!p) return fail(h, LBM_EINVAL, "null params");
     int Q, D;
     if (lattice_dims(p->lattice, &Q, &D) != LBM_OK) return fail(h, LBM_EINVAL, "unknown lattice %d", p->lattice);
-    if (p->stats != LBM_FERMI_DIRAC && p->stats != LBM_HERMITE)
+    if (p->stats != LBM_FERMI_DIRAC && p->stats != LBM_BOSE_EINSTEIN && p->stats != LBM_HERMITE)
         return fail(h, LBM_EINVAL, "unknown weight function %d", p->stats);
     if (p->storage != LBM_F32 && p->storage != LBM_F16 && p->storage != LBM_BF16)
         return fail(h, LBM_EINVAL, "unknown storage %d", p->storage);
@@ -142,6 +142,9 @@ int validate(const lbm_params *p, lbm_t h, Sizes *sz)
         return fail(h, LBM_EINVAL, "F16 storage: dev_scale_log2 must be in 0..40");
     if (p->stats == LBM_FERMI_DIRAC && (!(p->theta > 0) || !std::isfinite(p->theta) || !std::isfinite(p->mu)))
         return fail(h, LBM_EINVAL, "Fermi-Dirac weight needs finite theta > 0 and finite mu");
+    if (p->stats == LBM_BOSE_EINSTEIN && (!(p->theta > 0) || !std::isfinite(p->theta) || !(p->mu < 0) ||
+                                          !std::isfinite(p->mu)))
+        return fail(h, LBM_EINVAL, "Bose-Einstein weight needs finite theta > 0 and finite mu < 0");
     if (p->forcing != LBM_FORCE_SOURCE && p->forcing != LBM_FORCE_SHIFT)
         return fail(h, LBM_EINVAL, "unknown forcing scheme %d", p->forcing);
     if (p->slip & ~(LBM_SLIP_Y | LBM_SLIP_Z)) return fail(h, LBM_EINVAL, "slip: only LBM_SLIP_Y and LBM_SLIP_Z bits");

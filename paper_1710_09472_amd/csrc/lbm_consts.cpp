@@ -43,6 +43,7 @@ void gauss_legendre(int n, std::vector<long double> &x, std::vector<long double>
 long double omega(int stats, long double xi, long double theta, long double mu, int D)
 {
     if (stats == LBM_HERMITE) return std::exp(-0.5L * xi * xi) / std::pow(2.0L * (long double)M_PI, 0.5L * D);
+    if (stats == LBM_BOSE_EINSTEIN) return 1.0L / std::expm1((xi * xi - mu) / theta);  // mu < 0
     // 1/(exp((xi^2 - mu)/theta) + 1), written to stay finite for large arguments
     const long double a = (xi * xi - mu) / theta;
     if (a > 0) {
@@ -63,14 +64,18 @@ int weight_integrals(int stats, int D, double theta, double mu, double out[4])
         // (kept analytic; the quadrature path is used for every other weight)
         return LBM_OK;
     }
-    if (stats != LBM_FERMI_DIRAC) return LBM_EINVAL;
+    if (stats != LBM_FERMI_DIRAC && stats != LBM_BOSE_EINSTEIN) return LBM_EINVAL;
     if (!(theta > 0) || !std::isfinite(theta) || !std::isfinite(mu)) return LBM_EINVAL;
+    if (stats == LBM_BOSE_EINSTEIN && !(mu < 0)) return LBM_EINVAL;
     // The integrand is negligible beyond xi^2 = mu + 80 theta (omega < e^-80). Panels
-    // are narrower than the width of the Fermi edge (~theta/2 in xi near xi^2 = mu);
-    // nodes, weights and sums are carried in long double and rounded once at the end.
+    // are narrower than the width of the Fermi edge (~theta/2 in xi near xi^2 = mu), or,
+    // for the Bose-Einstein weight, than a quarter of its scales sqrt(theta) and
+    // sqrt(|mu|); nodes, weights and sums are carried in long double and rounded once.
     const long double th = theta, m = mu;
     const long double xmax = std::sqrt(std::fmax(mu, 0.0) + 80.0 * theta);
-    const long double h = std::fmin(1e-3L, 0.25L * th / std::fmax(1.0L, xmax));
+    const long double h = stats == LBM_FERMI_DIRAC
+                              ? std::fmin(1e-3L, 0.25L * th / std::fmax(1.0L, xmax))
+                              : std::fmin(1e-3L, 0.25L * std::sqrt(std::fmin(th, std::fabs(m))));
     const int npan = (int)std::ceil(xmax / h);
     std::vector<long double> gx, gw;
     gauss_legendre(10, gx, gw);

@@ -15,7 +15,7 @@ PKG = Path(__file__).resolve().parent
 LIB_PATH = PKG / "liblbm_hip.so"
 
 LATTICES = {"D2V9": 0, "D3V19": 1, "D3V15": 2}
-STATS = {"fd": 0, "hermite": 2}
+STATS = {"fd": 0, "be": 1, "hermite": 2}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 FORCING = {"source": 0, "shift": 1}
 SLIP_Y, SLIP_Z = 1, 2

@@ -45,6 +45,28 @@ def test_constants_match_oracle(lattice, D):
         assert abs(c["what"][sh] / float(lw["w"][sh] / k.I0) - 1) < 1e-14
 
 
+def test_bose_einstein_constants_match_oracle():
+    """The library's quadrature of the Bose-Einstein weight against the oracle (mpmath)."""
+    from oracle import constants as K
+
+    for lattice, D in (("D2V9", 2), ("D3V19", 3)):
+        for theta, mu in ((1.0, -0.1), (0.5, -2.0)):
+            c = lbm.compute_constants(lattice, "be", theta, mu)
+            k = K.coefficients(D, "be", theta, mu)
+            lw = K.lattice_weights(lattice, "be", theta, mu)
+            for name, ref in (("I0", k.I0), ("I2", k.I2), ("I4", k.I4), ("c2p", k.c2p), ("cs", k.cs)):
+                assert abs(c[name] / float(ref) - 1) < 1e-13, (lattice, theta, name)
+            # cbar_2 = c_2 (Delta_2 - 1)/D cancels near the Boltzmann limit (Delta_2 -> 1):
+            # compared on the scale of c_2
+            assert abs(c["c2bar"] - float(k.c2bar)) < 1e-13 * float(k.c2), (lattice, theta)
+            for sh in (0, 1, 2):
+                assert abs(c["w"][sh] / float(lw["w"][sh]) - 1) < 1e-13
+    lib = lbm.load_library()
+    out = lbm.LbmConstants()
+    bad = lbm.make_params("D2V9", stats="be", theta=1.0, mu=0.1)  # mu >= 0: no BE weight
+    assert lib.lbm_compute_constants(ctypes.byref(bad), ctypes.byref(out)) == lbm.LBM_EINVAL
+
+
 @pytest.mark.parametrize("lattice,fname", [("D2V9", "paper_constants_2d.txt"), ("D3V19", "paper_constants_3d.txt")])
 def test_constants_match_printed_tables(lattice, fname):
     """The library's FP64 constants against the printed 24-digit tables of Sec. 9.1."""

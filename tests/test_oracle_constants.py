@@ -239,3 +239,63 @@ def test_orthonormality(D):
                 assert abs(got - want) < 1e-13, ((i, j), (l, m), got, want)
     finally:
         mp.mp.dps = 40
+
+
+# Bose-Einstein parameters for the tests (the paper gives none): fugacity e^(mu/theta).
+BE_PARAMS = [(1.0, -0.1), (0.5, -2.0)]
+
+
+@pytest.mark.parametrize("D", [2, 3])
+@pytest.mark.parametrize("stats,theta,mu", [("fd", "1/270", 1.0), ("fd", 0.3, 0.4)] +
+                         [("be", t, m) for t, m in BE_PARAMS])
+def test_integrals_polylog_closed_form(D, stats, theta, mu):
+    """Sec. 2: rho = (2 pi theta')^(D/2) g_(D/2)(z) with g_nu(z) = -Li_nu(-z) (FD) or
+    Li_nu(z) (BE); in the xi^2/theta scaling of Sec. 9.1 (theta' = theta/2) the weight
+    integrals are I_2N = (theta/2)^N (pi theta)^(D/2) g_(D/2+N)(e^(mu/theta)). mpmath's
+    polylog is a route independent of the quadrature."""
+    th = mp.mpf(1) / 270 if theta == "1/270" else mp.mpf(theta)
+    z = mp.exp(mp.mpf(mu) / th)
+    for N in range(3):
+        s = mp.mpf(D) / 2 + N
+        g = -mp.polylog(s, -z) if stats == "fd" else mp.polylog(s, z)
+        want = (th / 2) ** N * (mp.pi * th) ** (mp.mpf(D) / 2) * mp.re(g)
+        got = K.weight_integral(D, 2 * N, stats, theta, mu)
+        assert abs(got / want - 1) < mp.mpf(10) ** -28, (N, got, want)
+
+
+@pytest.mark.parametrize("D", [2, 3])
+@pytest.mark.parametrize("stats", ["fd", "be"])
+def test_nondegenerate_limit(D, stats):
+    """For z = e^(mu/theta) -> 0 both semiclassical weights tend to the Maxwell-Boltzmann
+    Gaussian, whose moments give J_2 = I_2^2/(I_4 I_0) = 1 exactly; the correction is
+    O(z) (z = e^-40 here)."""
+    k = K.coefficients(D, stats, 1.0, -40.0)
+    assert abs(k.J2 - 1) < 1e-16
+
+
+@pytest.mark.parametrize("lattice", ["D2V9", "D3V19"])
+@pytest.mark.parametrize("theta,mu", BE_PARAMS)
+def test_bose_einstein_weights_positive(lattice, theta, mu):
+    """The quadratures of Sec. 8 need positive weights (true here: J_2 < 1 for BE)."""
+    lw = K.lattice_weights(lattice, "be", theta, mu)
+    assert all(float(v) > 0 for v in lw["w"].values())
+    assert K.coefficients(K.LATTICE_DIM[lattice], "be", theta, mu).J2 < 1
+
+
+def test_density_mu_2d_closed_forms_and_inverse():
+    """Sec. 9.1: in 2D g_1 is elementary, rho = pi theta ln(1 + e^(mu/theta)) (FD, and
+    rho ~ pi mu for mu/theta >> 1) and rho = -pi theta ln(1 - e^(mu/theta)) (BE);
+    mu_from_density inverts density_from_mu (2D and 3D)."""
+    th = mp.mpf(1) / 270
+    for mu in (-0.02, 0.3, 1.0):
+        r = K.density_from_mu(2, "fd", "1/270", mu)
+        assert abs(r / (mp.pi * th * mp.log(1 + mp.exp(mu / th))) - 1) < mp.mpf(10) ** -28
+    assert abs(K.density_from_mu(2, "fd", "1/270", 1.0) / mp.pi - 1) < mp.mpf(10) ** -30
+    for theta, mu in BE_PARAMS:
+        r = K.density_from_mu(2, "be", theta, mu)
+        assert abs(r / (-mp.pi * theta * mp.log(1 - mp.exp(mu / mp.mpf(theta)))) - 1) < mp.mpf(10) ** -28
+    for D in (2, 3):
+        for stats, theta, mu in (("fd", "1/270", 1.0), ("fd", "1/270", 0.05), ("be", 1.0, -0.1), ("be", 0.5, -2.0)):
+            r = K.density_from_mu(D, stats, theta, mu)
+            back = K.mu_from_density(D, r, stats, theta)
+            assert abs(back - mu) < mp.mpf(10) ** -20 * max(1, abs(mu)), (D, stats, mu, back)
