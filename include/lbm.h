@@ -201,6 +201,21 @@ int lbm_adjoint_seed(lbm_t h, int axis, double norm, float *lam);
 int lbm_adjoint_step(lbm_t h, const void *state, const float *lam_in, float *lam_out,
                      float *grad_s, double *grad_scalars);
 
+/* Density from chemical potential, Sec. 9.1-9.2: rho = (pi theta)^(D/2) g_(D/2)(e^(mu/theta))
+ * with g_nu(z) = -Li_nu(-z) (LBM_FERMI_DIRAC) or Li_nu(z) (LBM_BOSE_EINSTEIN); D from
+ * p->lattice, the weight from p->stats, theta from p->theta (other fields ignored). In 2D
+ * g_1 is elementary; in 3D g_3/2 is integrated in FP64 per element (~1e-14 relative).
+ * mu, rho: device double[n]. Async on `stream` (hipStream_t, NULL = default). The
+ * Bose-Einstein weight needs mu < 0 (NaN otherwise). Errors: LBM_EINVAL (Hermite
+ * weight, theta <= 0, null pointers), LBM_EDEVICE. Not part of the time step: the paper
+ * uses it to set initial conditions and to report fields. */
+int lbm_density_from_mu(const lbm_params *p, const double *mu, double *rho, size_t n, void *stream);
+
+/* The inverse: mu from rho > 0 (closed form in 2D, Newton's method on g_3/2 in 3D).
+ * NaN where no mu exists: rho <= 0, and Bose-Einstein 3D densities at or above
+ * (pi theta)^(3/2) zeta(3/2) (condensation). Same arguments and errors as above. */
+int lbm_mu_from_density(const lbm_params *p, const double *rho, double *mu, size_t n, void *stream);
+
 void lbm_destroy(lbm_t h);
 const char *lbm_last_error(lbm_t h);
 const char *lbm_status_string(int status);

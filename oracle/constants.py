@@ -197,17 +197,31 @@ def density_from_mu(D: int, stats: str = "fd", theta="1/270", mu=1.0) -> mp.mpf:
 
 
 def mu_from_density(D: int, rho, stats: str = "fd", theta="1/270") -> mp.mpf:
-    """The inverse of density_from_mu by secant iteration on mu (rho is increasing in
-    mu). Starting points: the degenerate estimate (D rho Gamma(D/2) / (2 pi^(D/2)))^(2/D)
-    for FD (Sommerfeld's leading term) and theta ln(rho / (pi theta)^(D/2)) (the
-    Boltzmann limit) for BE."""
+    """The inverse of density_from_mu (rho increases with mu) by the Illinois method on a
+    bracket, applied to log rho. The bracket starts at the degenerate estimate (D rho Gamma(D/2) /
+    (2 pi^(D/2)))^(2/D) for FD (Sommerfeld's leading term) and at the Boltzmann estimate
+    theta ln(rho / (pi theta)^(D/2)) for BE, and widens until it changes sign; for BE it
+    stays below mu = 0 (no mu exists above the density there, the 3D condensation)."""
     th = mp.mpf(1) / 270 if theta == "1/270" else mp.mpf(theta)
     rho = mp.mpf(rho)
+    # in log rho, which is near linear in mu both where rho ~ e^(mu/theta) and where
+    # rho ~ mu^(D/2), so the bracketed iteration converges quickly
+    g = lambda m: mp.log(weight_integral(D, 0, stats, th, m)) - mp.log(rho)
     if stats == "fd":
         x0 = (D * rho * mp.gamma(mp.mpf(D) / 2) / (2 * mp.pi ** (mp.mpf(D) / 2))) ** (mp.mpf(2) / D)
-        x0 = max(x0, th)
+        a, b, k = x0 - th, x0 + th, 0
+        while g(a) > 0:
+            k += 1
+            a = x0 - th * 2 ** k
+        k = 0
+        while g(b) < 0:
+            k += 1
+            b = x0 + th * 2 ** k
     else:
-        x0 = min(th * mp.log(rho / (mp.pi * th) ** (mp.mpf(D) / 2)), -th / 10)
-    g = lambda m: weight_integral(D, 0, stats, th, m) - rho
-    return mp.findroot(g, (x0, x0 * (1 + mp.mpf(1) / 1000) if x0 != 0 else th / 1000), solver="secant",
-                       tol=mp.mpf(10) ** (-30))
+        b = -th * mp.mpf(10) ** -30
+        if g(b) <= 0:
+            raise ValueError("no mu < 0 gives this density (Bose-Einstein condensation)")
+        a = min(th * mp.log(rho / (mp.pi * th) ** (mp.mpf(D) / 2)), -th / 10)
+        while g(a) > 0:
+            a *= 2
+    return mp.findroot(g, (a, b), solver="illinois", tol=mp.mpf(10) ** -32, maxsteps=400, verify=False)

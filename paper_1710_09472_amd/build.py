@@ -1,7 +1,8 @@
 """Build the HIP library ``liblbm_hip.so`` in-tree for gfx950.
 
-Sources: ``csrc/lbm_kernels.hip`` (device kernels and launchers), ``csrc/lbm_capi.cpp``
-(the C ABI of ``include/lbm.h``) and ``csrc/lbm_consts.cpp`` (host FP64 constants).
+Sources: ``csrc/lbm_kernels.hip`` (device kernels and launchers), ``csrc/lbm_density.hip``
+(rho <-> mu), ``csrc/lbm_capi.cpp`` (the C ABI of ``include/lbm.h``) and
+``csrc/lbm_consts.cpp`` (host FP64 constants).
 Every source goes through hipcc with packed-FP32 instruction selection disabled.
 
 Usage: ``python -m paper_1710_09472_amd.build`` or ``build()`` from Python.
@@ -19,7 +20,7 @@ CSRC = PKG / "csrc"
 INCLUDE = ROOT / "include"
 BUILD = PKG / "_build"
 LIB = PKG / "liblbm_hip.so"
-SOURCES = ["lbm_kernels.hip", "lbm_capi.cpp", "lbm_consts.cpp"]
+SOURCES = ["lbm_kernels.hip", "lbm_density.hip", "lbm_capi.cpp", "lbm_consts.cpp"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 

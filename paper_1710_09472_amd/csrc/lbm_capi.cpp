@@ -392,6 +392,32 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *s
 
 void lbm_destroy(lbm_t h) { delete h; }
 
+namespace {
+int density_common(const lbm_params *p, const double *in, double *out, size_t n, void *stream, bool to_mu)
+{
+    if (!p) return fail(nullptr, LBM_EINVAL, "null params");
+    int Q, D;
+    if (lattice_dims(p->lattice, &Q, &D) != LBM_OK) return fail(nullptr, LBM_EINVAL, "unknown lattice %d", p->lattice);
+    if (p->stats != LBM_FERMI_DIRAC && p->stats != LBM_BOSE_EINSTEIN)
+        return fail(nullptr, LBM_EINVAL, "rho(mu) needs the Fermi-Dirac or Bose-Einstein weight");
+    if (!(p->theta > 0) || !std::isfinite(p->theta)) return fail(nullptr, LBM_EINVAL, "theta must be finite and > 0");
+    if (n > 0 && (!in || !out)) return fail(nullptr, LBM_EINVAL, "null array");
+    const hipError_t e = launch_density(D, p->stats, p->theta, in, out, n, to_mu, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(nullptr, LBM_EDEVICE, "density kernel launch: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+}  // namespace
+
+int lbm_density_from_mu(const lbm_params *p, const double *mu, double *rho, size_t n, void *stream)
+{
+    return density_common(p, mu, rho, n, stream, false);
+}
+
+int lbm_mu_from_density(const lbm_params *p, const double *rho, double *mu, size_t n, void *stream)
+{
+    return density_common(p, rho, mu, n, stream, true);
+}
+
 int lbm_init(lbm_t h, const double *rho, const double *u)
 {
     if (!h) return fail(nullptr, LBM_EINVAL, "null handle");

@@ -147,6 +147,9 @@ struct AdjointArgs {
 // Launchers (lbm_kernels.hip). Each returns hipSuccess or the launch error.
 // force: 0 no field, 1 E only, 2 E and B.
 hipError_t launch_step(int lattice, int storage, int force, const StepArgs &a, hipStream_t st);
+// rho <-> mu of the weight (lbm_density.hip); to_mu selects the inverse
+hipError_t launch_density(int D, int stats, double theta, const double *in, double *out, size_t n, bool to_mu,
+                          hipStream_t st);
 // Per-node link masks from g.mask into links (link_mask_bytes(lattice) per node).
 hipError_t launch_links(int lattice, const Geometry &g, void *links, hipStream_t st);
 size_t link_mask_bytes(int lattice);

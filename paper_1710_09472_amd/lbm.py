@@ -27,6 +27,7 @@ EXPORTS = [
     "lbm_compute_constants", "lbm_lattice_info", "lbm_buffer_sizes", "lbm_create", "lbm_init",
     "lbm_step", "lbm_step_from", "lbm_moments", "lbm_current", "lbm_get_state", "lbm_set_state",
     "lbm_export_f64", "lbm_set_fields", "lbm_set_tau", "lbm_adjoint_seed", "lbm_adjoint_step",
+    "lbm_density_from_mu", "lbm_mu_from_density",
     "lbm_destroy", "lbm_last_error", "lbm_status_string",
 ]
 
@@ -87,6 +88,8 @@ def load_library() -> ctypes.CDLL:
         lib.lbm_set_tau.argtypes = [vp, d]
         lib.lbm_adjoint_seed.argtypes = [vp, i, d, vp]
         lib.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp]
+        lib.lbm_density_from_mu.argtypes = [vp, vp, vp, ctypes.c_size_t, vp]
+        lib.lbm_mu_from_density.argtypes = [vp, vp, vp, ctypes.c_size_t, vp]
         lib.lbm_destroy.argtypes = [vp]
         lib.lbm_destroy.restype = None
         lib.lbm_last_error.argtypes = [vp]
@@ -138,6 +141,29 @@ def compute_constants(lattice="D2V9", stats="fd", theta=1.0 / 270.0, mu=1.0) -> 
         v = getattr(out, name)
         res[name] = list(v) if hasattr(v, "__len__") else float(v)
     return res
+
+
+def _density_convert(fn_name, x, lattice, stats, theta):
+    import torch
+
+    lib = load_library()
+    x = torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+    out = torch.empty_like(x)
+    p = make_params(lattice, stats=stats, theta=theta)
+    stream = torch.cuda.current_stream()
+    _check(getattr(lib, fn_name)(ctypes.byref(p), _ptr(x), _ptr(out), ctypes.c_size_t(x.numel()),
+                                 ctypes.c_void_p(stream.cuda_stream)))
+    return out
+
+
+def density_from_mu(mu, lattice="D2V9", stats="fd", theta=1.0 / 270.0):
+    """rho = (pi theta)^(D/2) g_(D/2)(e^(mu/theta)) elementwise on the GPU (float64 tensor)."""
+    return _density_convert("lbm_density_from_mu", mu, lattice, stats, theta)
+
+
+def mu_from_density(rho, lattice="D2V9", stats="fd", theta=1.0 / 270.0):
+    """The inverse of density_from_mu (NaN where no mu exists)."""
+    return _density_convert("lbm_mu_from_density", rho, lattice, stats, theta)
 
 
 def lattice_info(lattice="D2V9"):
