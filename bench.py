@@ -269,8 +269,7 @@ def main():
     mlups = N * args.steps / wall / 1e6
     alg = algorithmic_bytes(wl, sim.Q, elem)
     achieved = alg / t_launch / 1e9
-    dims = f"{wl.nx}x{wl.ny}" + (f"x{wl.nz}" if wl.nz > 1 else "")
-    traffic = traffic_from_profile(f"k_step_{wl.lattice}_{st}_{dims}")
+    traffic = traffic_from_profile(f"k_step_{wl.lattice}_{st}_{args.workload}")
     tot = sim.current()
     sim.close()
     del sim
