@@ -3,18 +3,20 @@
 // Layout: the state holds the post-collision populations of the previous step as
 // structure-of-arrays deviations d_a = f_a - what_a rho0 (FP32, FP16 x 2^k or BF16),
 // array a at offset a*stride, node n = x + nx*(y + ny*z). A step pulls
-// f_a(x) = g_a(x - e_a) from the neighbours, or g_abar(x) when x - e_a is solid
-// (halfway bounce-back), collides in FP32 registers and writes the node's Q values to
-// the other buffer: every population is read once and written once per step.
+// f_a(x) = g_a(x - e_a) from the neighbours (halfway bounce-back where x - e_a is solid,
+// specular reflection where it lies in a free-slip wall plane), collides in FP32
+// registers and writes the node's Q values to the other buffer: every population is read
+// once and written once per step.
 //
-// Launch: 256 threads (4 wave64) per block; each thread owns V consecutive nodes of a
-// row (V = 1, 2 or 4), so the arrays are read and written with V-wide vector accesses;
-// the one value of an x-shifted population that falls outside the thread's V nodes is
-// fetched with a scalar load (it lies in a neighbouring lane's cache line). All loads of
-// a thread are issued before any arithmetic. Blocks are remapped so that each of the 8
-// XCDs (which receive blocks round-robin) works on one contiguous slab of the grid.
-// Solid nodes are described by a per-node link mask built once: bit a set when
-// x - e_a is solid, top bit set when x itself is solid.
+// Launch: 256 threads (4 wave64) per block over part of one x row; each thread owns V
+// consecutive nodes (V = 1 or 2), so the arrays are read and written with V-wide vector
+// accesses; the one value of an x-shifted population that falls outside the thread's V
+// nodes is fetched with a scalar load (it lies in a neighbouring lane's cache line). All
+// loads of a thread are issued before any arithmetic. Where there are solids or soft
+// fields, blocks are remapped so that each of the 8 XCDs (which receive blocks
+// round-robin) works on one contiguous slab of the grid. Solid nodes are described by a
+// per-node link mask built once: bit a set when the pull of a into x bounces back, top
+// bit set when x itself is solid.
 #include "lbm_internal.h"
 
 #include <cstdlib>
