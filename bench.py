@@ -176,22 +176,30 @@ def adjoint_pipeline():
             "ratio_to_forward": round(bwd / fwd, 3), "dJ_dEx": float(gE[0]), "dJ_dtau": float(gT)}
 
 
+def kernel_code_hash() -> str:
+    """sha256 of the kernel source without // comments and blank lines: it changes with
+    the code, not with its comments."""
+    import hashlib
+
+    lines = []
+    for line in (ROOT / "paper_1710_09472_amd" / "csrc" / "lbm_kernels.hip").read_text().splitlines():
+        line = re.sub(r"//.*$", "", line).rstrip()
+        if line.strip():
+            lines.append(line)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()
+
+
 def traffic_from_profile(kernel_tag: str):
     """HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE + WRITE_SIZE,
     scaled by a copy-kernel calibration), read from the committed summary, if the
-    kernel source has not changed since it was taken; else None."""
+    kernel code has not changed since it was taken; else None."""
     f = PROFILE_DIR / f"{kernel_tag}_pmc.txt"
     if not f.exists():
         return None
     txt = f.read_text()
     m = re.search(r"^hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt, re.M)
-    h = re.search(r"^kernel_source_sha256:\s*([0-9a-f]+)", txt, re.M)
-    if not m or not h:
-        return None
-    import hashlib
-
-    src = (ROOT / "paper_1710_09472_amd" / "csrc" / "lbm_kernels.hip").read_bytes()
-    if hashlib.sha256(src).hexdigest() != h.group(1):
+    h = re.search(r"^kernel_code_sha256:\s*([0-9a-f]+)", txt, re.M)
+    if not m or not h or kernel_code_hash() != h.group(1):
         return None
     return float(m.group(1))
 
