@@ -74,9 +74,11 @@ def window_plan(wl: W.Workload, steps: int, core: int, centre):
 def oracle_window_fields(wl: W.Workload, steps: int, core: int, centre):
     """Oracle rho, u on the core block after `steps` steps, computed on a sub-window.
     Returns (global node indices of the core block, rho, u)."""
+    assert not wl.slip, "periodic sub-windows cannot hold free-slip planes"
     dims = (wl.nx, wl.ny, wl.nz)
     lo, size, core_lo = window_plan(wl, steps, core, centre)
-    sub = W.Workload(wl.name, wl.lattice, size[0], size[1], size[2], wl.tau, steps, wl.E, wl.B)
+    sub = W.Workload(wl.name, wl.lattice, size[0], size[1], size[2], wl.tau, steps, wl.E, wl.B,
+                     forcing=wl.forcing)
     sub.rho = W.window(wl.rho, dims, lo, size)
     sub.u = None if wl.u is None else W.window(wl.u, dims, lo, size, ncomp=wl.D)
     sub.mask = None if wl.mask is None else W.window(wl.mask, dims, lo, size)
