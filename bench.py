@@ -9,15 +9,17 @@ FP32 deviation storage, inputs resident in HBM.
 
 Prints one JSON line: MLUPS (value), ms per step, the roofline of the step kernel
 (algorithmic bytes per launch / measured average launch time, against 8 TB/s HBM3E),
-the FP16- and BF16-storage steps, the adjoint step relative to the forward step, and
-the FP64 CPU oracle timed on this host on a bounded sample of the same workload.
+the FP16- and BF16-storage steps, the adjoint step relative to the forward step, the
+in-place step (one state buffer, FP32 and FP16) with its two phases, and the FP64 CPU
+oracle timed on this host on a bounded sample of the same workload.
 
 --workload selects one of the other full-size workloads (the 256x128x128 D3V19 Hall
 duct, the 2048^2 D2V9 disk packing, the 128^3 D3V19 soft-porosity box) and --storage
 its storage format; those runs time the step alone (no FP16/BF16 or adjoint extras).
+--inplace times the in-place step (one state buffer) instead of the two-buffer step.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                       [--storage f32|f16|bf16] [--no-cpu-baseline] [--no-extras]
+                       [--storage f32|f16|bf16] [--inplace] [--no-cpu-baseline] [--no-extras]
 """
 from __future__ import annotations
 
@@ -120,6 +122,41 @@ def timed_steps(sim, steps: int, warmup: int):
     return wall, ev0.elapsed_time(ev1) * 1e-3
 
 
+def inplace_phases(sim, steps: int):
+    """Average durations of the two in-place kernels (the pull phase from the two-buffer
+    layout, then the local phase back), from HIP events around every launch. The handle
+    must be at even parity (an even number of steps since init)."""
+    import torch
+
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    evs[0].record(sim.stream)
+    for i in range(steps):
+        sim.step(1)
+        evs[i + 1].record(sim.stream)
+    torch.cuda.synchronize()
+    d = [evs[i].elapsed_time(evs[i + 1]) * 1e-3 for i in range(steps)]
+    return sum(d[0::2]) / len(d[0::2]), sum(d[1::2]) / len(d[1::2])
+
+
+def inplace_extra(wl, storage: str, k: int, steps: int, warmup: int):
+    """Throughput of the in-place (one-buffer) step on the workload's grid."""
+    from paper_1710_09472_amd.lbm import Simulation
+
+    sim = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E, B=wl.B, storage=storage,
+                     dev_scale_log2=k, mask=wl.mask, s=wl.s, forcing=wl.forcing, slip=wl.slip, inplace=True)
+    sim.init(wl.rho, wl.u)
+    w, e = timed_steps(sim, steps, warmup + (warmup % 2))
+    pull, local = inplace_phases(sim, 40)
+    elem = 4 if storage == "f32" else 2
+    alg = algorithmic_bytes(wl, sim.Q, elem)
+    sim.close()
+    return {"MLUPS": round(wl.N * steps / w / 1e6, 1), "ms_per_step": round(w / steps * 1e3, 5),
+            "achieved_GBs": round(alg / (e / steps) / 1e9, 1),
+            "pull_phase_ms": round(pull * 1e3, 5), "local_phase_ms": round(local * 1e3, 5),
+            "state_buffers": 1}
+
+
 def adjoint_ratio(wl, steps: int, warmup: int):
     """Average time of one adjoint step (reverse pull, transposed collision and force,
     FP64 per-wave partials of dJ/dE and dJ/dtau held across steps and reduced on the
@@ -177,15 +214,16 @@ def adjoint_pipeline():
 
 
 def kernel_code_hash() -> str:
-    """sha256 of the kernel source without // comments and blank lines: it changes with
-    the code, not with its comments."""
+    """sha256 of the step kernel's sources (the device header and the kernel file) without
+    // comments and blank lines: it changes with the code, not with its comments."""
     import hashlib
 
     lines = []
-    for line in (ROOT / "paper_1710_09472_amd" / "csrc" / "lbm_kernels.hip").read_text().splitlines():
-        line = re.sub(r"//.*$", "", line).rstrip()
-        if line.strip():
-            lines.append(line)
+    for name in ("lbm_device.h", "lbm_kernels.hip"):
+        for line in (ROOT / "paper_1710_09472_amd" / "csrc" / name).read_text().splitlines():
+            line = re.sub(r"//.*$", "", line).rstrip()
+            if line.strip():
+                lines.append(line)
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()
 
 
@@ -244,6 +282,8 @@ def main():
     ap.add_argument("--storage", default="f32", choices=("f32", "f16", "bf16"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the main step")
+    ap.add_argument("--inplace", action="store_true",
+                    help="time the in-place step (one state buffer) instead of the two-buffer step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB three times with a plain device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -270,14 +310,15 @@ def main():
     elem = 4 if st == "f32" else 2
     k16 = F16_SCALE[args.workload] if st == "f16" else 0
     sim = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E, B=wl.B, storage=st,
-                     dev_scale_log2=k16, mask=wl.mask, s=wl.s, forcing=wl.forcing, slip=wl.slip)
+                     dev_scale_log2=k16, mask=wl.mask, s=wl.s, forcing=wl.forcing, slip=wl.slip,
+                     inplace=args.inplace)
     sim.init(wl.rho, wl.u)
     wall, ev = timed_steps(sim, args.steps, args.warmup)
     t_launch = ev / args.steps
     mlups = N * args.steps / wall / 1e6
     alg = algorithmic_bytes(wl, sim.Q, elem)
     achieved = alg / t_launch / 1e9
-    traffic = traffic_from_profile(f"k_step_{wl.lattice}_{st}_{args.workload}")
+    traffic = None if args.inplace else traffic_from_profile(f"k_step_{wl.lattice}_{st}_{args.workload}")
     tot = sim.current()
     sim.close()
     del sim
@@ -300,12 +341,15 @@ def main():
                                                   "forward_ms_per_step": round(t_fwd * 1e3, 5),
                                                   "ratio_to_forward": round(t_adj / t_fwd, 3)},
                              "checkpointed_128cube": adjoint_pipeline()}
+        extras["inplace"] = {"f32": inplace_extra(wl, "f32", 0, args.steps, args.warmup),
+                             "f16": inplace_extra(wl, "f16", F16_SCALE["throughput_2d"], args.steps, args.warmup)}
 
-    kernel = f"k_step<{wl.lattice},{st.upper()}" + (",mask" if wl.mask is not None else "") + \
+    kernel = ("k_step_aa_pull+k_step_aa_local" if args.inplace else "k_step") + \
+        f"<{wl.lattice},{st.upper()}" + (",mask" if wl.mask is not None else "") + \
         (",slip" if wl.slip else "") + (",soft" if wl.s is not None else "") + \
         (",shift" if wl.forcing == "shift" else "") + ">"
     desc = WORKLOAD_DESC[args.workload] + {"f32": ", FP32", "f16": f", FP16 x 2^{k16}", "bf16": ", BF16"}[st] + \
-        " deviation storage"
+        " deviation storage" + (", in-place step (one state buffer)" if args.inplace else "")
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -331,6 +375,7 @@ def main():
     if default:
         out["storage16"] = extras.get("f16") and {"f16": extras["f16"], "bf16": extras["bf16"]}
         out["adjoint"] = extras.get("adjoint")
+        out["inplace"] = extras.get("inplace")
     out["mass_after_run"] = tot[0]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -131,13 +131,21 @@ int lbm_buffer_sizes(const lbm_params *p, size_t *state_bytes, size_t *work_byte
  *   mask    : device uint8[N], 1 = solid, or NULL (no solids)
  *   s       : device float[N] in [0, 1], partial bounce-back fraction (Walsh et al.
  *             2009 gray lattice, not in the paper), or NULL
- *   state_a, state_b : two device state buffers of state_bytes each (ping-pong)
+ *   state_a, state_b : two device state buffers of state_bytes each (ping-pong); with
+ *             state_b = NULL the handle keeps one buffer and every step updates it in
+ *             place (the AA access pattern of Bailey et al. 2009, not in the paper): a
+ *             step that starts from the two-buffer layout writes each node's
+ *             post-collision values where it pulled the opposite populations from (the
+ *             populations end up streamed), and the next step reads them at the node
+ *             and writes the two-buffer layout again. Same results, bit for bit, as two
+ *             buffers, with half the state memory; lbm_get_state always returns the
+ *             two-buffer layout.
  *   work    : device buffer of work_bytes
  *   stream  : hipStream_t (NULL = default stream)
  * Errors: LBM_EINVAL (tau <= 1/2, bad sizes, B_x/B_y or E_z in 2D, nz != 1 for D2V9,
- * null buffer, F16 scale out of range, unknown forcing, slip bits other than Y/Z, Z
- * slip in 2D, a slip axis with fewer than 3 planes), LBM_EUNSUPPORTED (non-positive
- * weight), LBM_EDEVICE. On error *out is NULL. */
+ * null state_a or work, state_a == state_b, F16 scale out of range, unknown forcing,
+ * slip bits other than Y/Z, Z slip in 2D, a slip axis with fewer than 3 planes),
+ * LBM_EUNSUPPORTED (non-positive weight), LBM_EDEVICE. On error *out is NULL. */
 int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *state_a,
                void *state_b, void *work, void *stream, lbm_t *out);
 
@@ -148,12 +156,14 @@ int lbm_init(lbm_t h, const double *rho, const double *u);
 
 /* Advance nsteps >= 0 time steps (collide, force, partial bounce-back, stream,
  * halfway bounce-back and free-slip walls: the discrete BGK update of Sec. 9.1 with
- * the forcing of Sec. 7). Async. */
+ * the forcing of Sec. 7). With one state buffer (state_b = NULL) the steps alternate
+ * between the two in-place kernels. Async. */
 int lbm_step(lbm_t h, int nsteps);
 
 /* One step from the state in `src` into `dst` (device state buffers of state_bytes,
- * distinct, neither need be the handle's own); the handle's state is not touched.
- * Used to recompute trajectories for the adjoint. Async. */
+ * distinct, neither need be the handle's own; two-buffer layout, as lbm_get_state
+ * writes it); the handle's state is not touched. Used to recompute trajectories for
+ * the adjoint. Async. */
 int lbm_step_from(lbm_t h, const void *src, void *dst);
 
 /* Fields of the current state (pre-collision): rho (device float[N]) and u (device
@@ -166,7 +176,10 @@ int lbm_moments(lbm_t h, float *rho, float *u);
 int lbm_current(lbm_t h, double out[4]);
 
 /* Copy the current state to / from a caller device buffer of state_bytes (the
- * library's opaque layout: post-collision populations of the previous step). Async. */
+ * library's opaque two-buffer layout: post-collision populations of the previous step).
+ * With one state buffer after an odd number of steps, lbm_get_state rearranges the
+ * in-place layout into dst with a kernel (dst must not be state_a, LBM_EINVAL);
+ * lbm_set_state restarts the in-place sequence from the two-buffer layout. Async. */
 int lbm_get_state(lbm_t h, void *dst);
 int lbm_set_state(lbm_t h, const void *src);
 

@@ -37,6 +37,8 @@ struct lbm_s {
     const float *s = nullptr;
     void *buf[2] = {nullptr, nullptr};
     int cur = 0;
+    bool aa = false;  // one state buffer: in-place steps (AA pattern)
+    int parity = 0;   // in-place steps since the last even layout, mod 2
     unsigned char *work = nullptr;
     hipStream_t stream = nullptr;
     Geometry g{};
@@ -345,7 +347,7 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *s
         return fail(nullptr, rc == LBM_OK ? LBM_EUNSUPPORTED : rc,
                     "D3V15 is not supported (its rest weight is negative under the electron weight)");
     }
-    if (!state_a || !state_b || !work) return fail(nullptr, LBM_EINVAL, "state_a, state_b and work are required");
+    if (!state_a || !work) return fail(nullptr, LBM_EINVAL, "state_a and work are required");
     if (state_a == state_b) return fail(nullptr, LBM_EINVAL, "state_a and state_b must be distinct buffers");
     lbm_s *h = new (std::nothrow) lbm_s;
     if (!h) return fail(nullptr, LBM_EDEVICE, "out of host memory");
@@ -364,6 +366,7 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *s
     h->s = s;
     h->buf[0] = state_a;
     h->buf[1] = state_b;
+    h->aa = state_b == nullptr;
     h->work = static_cast<unsigned char *>(work);
     h->stream = static_cast<hipStream_t>(stream);
     h->g.nx = p->nx;
@@ -432,6 +435,7 @@ int lbm_init(lbm_t h, const double *rho, const double *u)
     const hipError_t e = launch_init(h->p.lattice, h->p.storage, a, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "init kernel launch");
     h->initialized = true;
+    h->parity = 0;
     return LBM_OK;
 }
 
@@ -446,6 +450,15 @@ int lbm_step(lbm_t h, int nsteps)
     a.links = links_of(h);
     a.remap = use_xcd_remap(h->p.lattice, has_solids(h), h->s != nullptr);
     const int force = force_level(h);
+    if (h->aa) {
+        a.src = a.dst = h->buf[0];
+        for (int t = 0; t < nsteps; ++t) {
+            const hipError_t e = launch_step_aa(h->p.lattice, h->p.storage, force, h->parity, a, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "in-place step kernel launch");
+            h->parity ^= 1;
+        }
+        return LBM_OK;
+    }
     for (int t = 0; t < nsteps; ++t) {
         a.src = h->buf[h->cur];
         a.dst = h->buf[h->cur ^ 1];
@@ -484,6 +497,7 @@ static int gather_common(lbm_t h, const void *state, float *rho, float *u, doubl
     a.f64 = f64;
     a.partials = parts;
     a.N = h->N;
+    a.odd = (!state && h->aa && h->parity) ? 1 : 0;
     for (int k = 0; k < 4; ++k) a.what_rho0[k] = h->k.what[k] * h->p.rho0;
     const hipError_t e = launch_gather(h->p.lattice, h->p.storage, a, kReduceBlocks, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "gather kernel launch");
@@ -532,6 +546,18 @@ int lbm_get_state(lbm_t h, void *dst)
 {
     if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
     if (!dst) return fail(h, LBM_EINVAL, "dst is required");
+    if (h->aa && h->parity) {
+        if (dst == h->buf[0]) return fail(h, LBM_EINVAL, "dst must not be the handle's own state buffer");
+        StepArgs a{};
+        a.g = h->g;
+        a.ph = h->ph;
+        a.links = links_of(h);
+        a.src = h->buf[0];
+        a.dst = dst;
+        const hipError_t e = launch_canon(h->p.lattice, h->p.storage, a, h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "state layout kernel launch");
+        return LBM_OK;
+    }
     const hipError_t e = hipMemcpyAsync(dst, h->buf[h->cur], (size_t)h->Q * h->stride * h->elem,
                                         hipMemcpyDeviceToDevice, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "state copy");
@@ -546,6 +572,7 @@ int lbm_set_state(lbm_t h, const void *src)
                                         hipMemcpyDeviceToDevice, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "state copy");
     h->initialized = true;
+    h->parity = 0;
     return LBM_OK;
 }
 

@@ -129,6 +129,7 @@ struct GatherArgs {
     double *partials; // nullable (reduction)
     double what_rho0[4];  // what_k rho0 in FP64 (export of full populations)
     int N;
+    int odd;          // src is in the odd layout of the in-place step
 };
 
 struct AdjointArgs {
@@ -163,6 +164,11 @@ hipError_t launch_reduce_final(const double *partials, int nparts, int ncomp, do
 int step_vector_width(int lattice, int storage, int nx);
 int use_xcd_remap(int lattice, bool mask, bool soft);
 hipError_t launch_adjoint(int lattice, int storage, bool mag, const AdjointArgs &a, hipStream_t st);
+// In-place step (lbm_aa.hip), a.src == a.dst: phase 0 takes the state from the two-buffer
+// layout to the odd layout, phase 1 back. launch_canon writes the two-buffer layout of an
+// odd-layout state a.src into a.dst (a distinct buffer).
+hipError_t launch_step_aa(int lattice, int storage, int force, int phase, const StepArgs &a, hipStream_t st);
+hipError_t launch_canon(int lattice, int storage, const StepArgs &a, hipStream_t st);
 hipError_t launch_seed(int lattice, const Geometry &g, float value_per_unit_e, int axis, float *lam,
                        hipStream_t st);
 

@@ -17,14 +17,9 @@
 // round-robin) works on one contiguous slab of the grid. Solid nodes are described by a
 // per-node link mask built once: bit a set when the pull of a into x bounces back, top
 // bit set when x itself is solid.
-#include "lbm_internal.h"
+#include "lbm_device.h"
 
 #include <cstdlib>
-#include <type_traits>
-
-#ifndef LBM_NT_STORE
-#define LBM_NT_STORE 1
-#endif
 
 namespace lbm {
 
@@ -58,508 +53,6 @@ int use_xcd_remap(int lattice, bool mask, bool soft)
 namespace {
 
 // ---------------------------------------------------------------------------------
-// Storage codecs: deviation <-> stored value (round to nearest even).
-// ---------------------------------------------------------------------------------
-template <int ST>
-struct Codec;
-
-template <>
-struct Codec<LBM_F32> {
-    using T = float;
-    static __device__ __forceinline__ float dec(T v, float) { return v; }
-    static __device__ __forceinline__ T enc(float f, float) { return f; }
-};
-
-template <>
-struct Codec<LBM_F16> {
-    using T = _Float16;
-    // stored value = d * 2^k; the scale is a power of two, so scaling is exact
-    static __device__ __forceinline__ float dec(T v, float inv_scale) { return (float)v * inv_scale; }
-    static __device__ __forceinline__ T enc(float f, float scale) { return (T)(f * scale); }
-};
-
-template <>
-struct Codec<LBM_BF16> {
-    using T = __bf16;
-    static __device__ __forceinline__ float dec(T v, float) { return (float)v; }
-    static __device__ __forceinline__ T enc(float f, float) { return (T)f; }
-};
-
-// Where a bounced population is kept between steps (halfway bounce-back: the value
-// pulled into fluid x as population q, when x - e_q is solid, is f*_qbar(x)):
-// * own slot (FP32): it stays in slot qbar of x, where the step stores it anyway, and
-//   the pull at x reloads it from there for the links of x;
-// * solid slot (16-bit): the step also stores it in slot q of the solid node x - e_q,
-//   so every pull is a plain read of x - e_q and waits on no link mask.
-// Measured on MI355X: the solid slot wins where both state buffers stay in the 256 MB
-// Infinity Cache (16-bit 2048^2 disks 1.3x); with FP32 buffers beyond it, its scattered
-// partial-line stores cost more than the reloads (FP32 2048^2 disks 0.89x).
-template <int ST>
-constexpr bool kSolidSlotBB = ST != LBM_F32;
-
-template <int ST, int V>
-struct VecT {
-    typedef typename Codec<ST>::T type __attribute__((ext_vector_type(V)));
-};
-template <int ST>
-struct VecT<ST, 1> {
-    using type = typename Codec<ST>::T;
-};
-
-// Non-temporal loads: each value is read once per step (measured on MI355X: +3 % on the
-// 4096^2 FP32 step, +5 % on the FP32 duct and the 16-bit disk packing). The x-shifted
-// populations of one-node tiles and the edge values of V-wide tiles are loaded through
-// the cache instead (gather_tile): their lines straddle the neighbouring tile's.
-template <int ST, int V>
-__device__ __forceinline__ void vload(const typename Codec<ST>::T *p, float inv_scale, float *f)
-{
-    if constexpr (V == 1) {
-        f[0] = Codec<ST>::dec(__builtin_nontemporal_load(p), inv_scale);
-    } else {
-        using VT = typename VecT<ST, V>::type;
-        const VT v = __builtin_nontemporal_load(reinterpret_cast<const VT *>(p));
-#pragma unroll
-        for (int i = 0; i < V; ++i) f[i] = Codec<ST>::dec(v[i], inv_scale);
-    }
-}
-
-template <int ST, int V>
-__device__ __forceinline__ void vstore(typename Codec<ST>::T *p, float scale, const float *f)
-{
-    if constexpr (V == 1) {
-        const typename Codec<ST>::T v = Codec<ST>::enc(f[0], scale);
-#if LBM_NT_STORE
-        __builtin_nontemporal_store(v, p);
-#else
-        *p = v;
-#endif
-    } else {
-        using VT = typename VecT<ST, V>::type;
-        VT v;
-#pragma unroll
-        for (int i = 0; i < V; ++i) v[i] = Codec<ST>::enc(f[i], scale);
-#if LBM_NT_STORE
-        __builtin_nontemporal_store(v, reinterpret_cast<VT *>(p));
-#else
-        *reinterpret_cast<VT *>(p) = v;
-#endif
-    }
-}
-
-// base + idx elements with the byte offset formed in 32 bits, so that a load or store
-// takes the uniform base in SGPRs and one VGPR offset instead of a 64-bit lane address.
-// Every array indexed this way is below 4 GiB (Q * stride < 2^31 elements).
-template <class T>
-__device__ __forceinline__ T *at32(T *base, unsigned idx)
-{
-    using C = std::conditional_t<std::is_const_v<T>, const char, char>;
-    return reinterpret_cast<T *>(reinterpret_cast<C *>(base) + idx * (unsigned)sizeof(T));
-}
-
-// ---------------------------------------------------------------------------------
-// Lattice helpers (all indices compile-time after unrolling).
-// ---------------------------------------------------------------------------------
-template <int LAT, int q>
-__device__ __forceinline__ constexpr int shell()
-{
-    using L = Lat<LAT>;
-    return L::ex[q] * L::ex[q] + L::ey[q] * L::ey[q] + L::ez[q] * L::ez[q];
-}
-
-// e_q . v without adding zeros (0 + x cannot be folded in IEEE arithmetic).
-template <int LAT, int q>
-__device__ __forceinline__ float edot(const float *v)
-{
-    using L = Lat<LAT>;
-    constexpr int a = L::ex[q], b = L::ey[q], c = L::ez[q];
-    if constexpr (a == 0 && b == 0 && c == 0) {
-        return 0.f;
-    } else {
-        float r = 0.f;
-        bool first = true;
-        if constexpr (a != 0) {
-            r = a > 0 ? v[0] : -v[0];
-            first = false;
-        }
-        if constexpr (b != 0) {
-            const float t = b > 0 ? v[1] : -v[1];
-            r = first ? t : r + t;
-            first = false;
-        }
-        if constexpr (c != 0) {
-            const float t = c > 0 ? v[2] : -v[2];
-            r = first ? t : r + t;
-        }
-        return r;
-    }
-}
-
-// Unrolled compile-time loop over q.
-template <int Q, int q = 0, typename F>
-__device__ __forceinline__ void for_q(F &&f)
-{
-    if constexpr (q < Q) {
-        f(std::integral_constant<int, q>{});
-        for_q<Q, q + 1>(f);
-    }
-}
-
-template <int LAT>
-struct LinkMask;
-template <>
-struct LinkMask<LBM_D2V9> {
-    using T = uint16_t;
-    static constexpr T solid = (T)0x8000u;
-};
-template <>
-struct LinkMask<LBM_D3V19> {
-    using T = uint32_t;
-    static constexpr T solid = 0x80000000u;
-};
-
-// ---------------------------------------------------------------------------------
-// Thread -> nodes.
-// ---------------------------------------------------------------------------------
-// Block -> contiguous slab per XCD.
-__device__ __forceinline__ int xcd_remap(int bid, int nb)
-{
-    const int per = nb >> 3, rem = nb & 7;
-    const int xcd = bid & 7, k = bid >> 3;
-    return xcd * per + min(xcd, rem) + k;
-}
-
-__device__ __forceinline__ int wrapm(int i, int n) { return i == 0 ? n - 1 : i - 1; }
-__device__ __forceinline__ int wrapp(int i, int n) { return i == n - 1 ? 0 : i + 1; }
-
-struct Tile {
-    int x0, y, z;  // first node of this thread (clamped into the row)
-    int own;       // node index of x0
-    bool valid;    // the thread owns nodes
-};
-
-__device__ __forceinline__ int fast_div(int n, FastDiv f)
-{
-    return (int)(((uint64_t)(uint32_t)n * f.m) >> f.sh);
-}
-
-// Block bid covers kBlock * V nodes of one x row; ntx such blocks per row.
-template <int V>
-__device__ __forceinline__ Tile tile_of(const Geometry &g, int bid, int ntx, FastDiv div_ntx)
-{
-    const int row = fast_div(bid, div_ntx);
-    Tile t;
-    int x0 = ((bid - row * ntx) * kBlock + (int)threadIdx.x) * V;
-    t.valid = x0 < g.nx;
-    if (!t.valid) x0 = g.nx - V;
-    t.x0 = x0;
-    t.z = fast_div(row, g.div_ny);
-    t.y = row - t.z * g.ny;
-    t.own = x0 + g.nx * row;
-    return t;
-}
-
-__device__ __forceinline__ Tile tile_of(const Geometry &g, int bid) { return tile_of<1>(g, bid, g.ntx, g.div_ntx); }
-
-// Source of the pull of population q into node x0 + i of tile t: the row of x - e_q
-// (element offset of its first node) and the x index within that row.
-struct PullRows {
-    int ym, yp, zm, zp;
-    unsigned x0, xl, xr;
-};
-
-template <int V>
-__device__ __forceinline__ PullRows pull_rows(const Geometry &g, const Tile &t)
-{
-    PullRows r;
-    r.ym = wrapm(t.y, g.ny);
-    r.yp = wrapp(t.y, g.ny);
-    r.zm = wrapm(t.z, g.nz);
-    r.zp = wrapp(t.z, g.nz);
-    // lane offsets are unsigned 32-bit, so accesses use a scalar base and one VGPR offset
-    r.x0 = (unsigned)t.x0;
-    r.xl = t.x0 == 0 ? (unsigned)(g.nx - 1) : r.x0 - 1u;
-    r.xr = t.x0 + V >= g.nx ? 0u : r.x0 + (unsigned)V;
-    return r;
-}
-
-// Index of e_q with its y (fy) and/or z (fz) component reversed.
-template <int LAT>
-constexpr int reflected(int q, bool fy, bool fz)
-{
-    using L = Lat<LAT>;
-    for (int b = 0; b < L::Q; ++b)
-        if (L::ex[b] == L::ex[q] && L::ey[b] == (fy ? -L::ey[q] : L::ey[q]) &&
-            L::ez[b] == (fz ? -L::ez[q] : L::ez[q]))
-            return b;
-    return -1;
-}
-
-// Element offset of the value pulled into the row of tile t as population q: slot q of
-// the row of x - e_q; where that row is a free-slip wall plane, the specular source,
-// i.e. slot qr (e_q with the wall-normal components reversed) of the row of x itself
-// (the tile's row is uniform over the block, so this choice is a scalar one).
-template <int LAT, int q>
-__device__ __forceinline__ size_t pull_row(const Geometry &g, const Tile &t, const PullRows &r)
-{
-    using L = Lat<LAT>;
-    int sy = L::ey[q] > 0 ? r.ym : (L::ey[q] < 0 ? r.yp : t.y);
-    int sz = L::ez[q] > 0 ? r.zm : (L::ez[q] < 0 ? r.zp : t.z);
-    int p = q;
-    if (g.slip) {
-        const bool fy = L::ey[q] != 0 && (g.slip & LBM_SLIP_Y) && (sy == 0 || sy == g.ny - 1);
-        const bool fz = L::ez[q] != 0 && (g.slip & LBM_SLIP_Z) && (sz == 0 || sz == g.nz - 1);
-        if (fy) sy = t.y;
-        if (fz) sz = t.z;
-        constexpr int py = reflected<LAT>(q, true, false), pz = reflected<LAT>(q, false, true);
-        constexpr int pyz = reflected<LAT>(q, true, true);
-        p = fy ? (fz ? pyz : py) : (fz ? pz : q);
-    }
-    return (size_t)p * g.stride + (size_t)g.nx * (sy + g.ny * sz);
-}
-
-template <int LAT, int q, int V>
-__device__ __forceinline__ unsigned pull_x(const PullRows &r, int i)
-{
-    using L = Lat<LAT>;
-    if constexpr (L::ex[q] > 0) return i == 0 ? r.xl : r.x0 + (unsigned)(i - 1);
-    else if constexpr (L::ex[q] < 0) return i == V - 1 ? r.xr : r.x0 + (unsigned)(i + 1);
-    else return r.x0 + (unsigned)i;
-}
-
-// Pull the pre-collision deviations of the V nodes of tile t (link masks lk). With the
-// solid-slot convention every pull is a plain read of x - e_q; with the own-slot one the
-// populations whose source x - e_q is solid are then reloaded from slot qbar of x.
-template <int LAT, int ST, bool MASK, int V>
-__device__ __forceinline__ void gather_tile(const Geometry &g, const typename Codec<ST>::T *__restrict__ src,
-                                            float inv_scale, const Tile &t,
-                                            const typename LinkMask<LAT>::T *lk, float (&d)[V][Lat<LAT>::Q])
-{
-    using L = Lat<LAT>;
-    const PullRows r = pull_rows<V>(g, t);
-    for_q<L::Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        const typename Codec<ST>::T *base = src + pull_row<LAT, q>(g, t, r);
-        if constexpr (L::ex[q] == 0) {
-            float f[V];
-            vload<ST, V>(at32(base, r.x0), inv_scale, f);
-#pragma unroll
-            for (int i = 0; i < V; ++i) d[i][q] = f[i];
-        } else if constexpr (V == 1) {
-            d[0][q] = Codec<ST>::dec(*at32(base, L::ex[q] > 0 ? r.xl : r.xr), inv_scale);
-        } else if constexpr (L::ex[q] > 0) {  // from x - 1
-            float f[V];
-            vload<ST, V>(at32(base, r.x0), inv_scale, f);
-            d[0][q] = Codec<ST>::dec(*at32(base, r.xl), inv_scale);
-#pragma unroll
-            for (int i = 1; i < V; ++i) d[i][q] = f[i - 1];
-        } else {  // from x + 1
-            float f[V];
-            vload<ST, V>(at32(base, r.x0), inv_scale, f);
-#pragma unroll
-            for (int i = 0; i < V - 1; ++i) d[i][q] = f[i + 1];
-            d[V - 1][q] = Codec<ST>::dec(*at32(base, r.xr), inv_scale);
-        }
-    });
-    if constexpr (MASK && !kSolidSlotBB<ST>) {
-        // one branch for the whole tile: most tiles have no solid neighbour at all
-        typename LinkMask<LAT>::T any = 0;
-#pragma unroll
-        for (int i = 0; i < V; ++i) any |= lk[i] & (typename LinkMask<LAT>::T)~LinkMask<LAT>::solid;
-        if (any) {
-            const unsigned own = (unsigned)t.own;
-#pragma unroll
-            for (int i = 0; i < V; ++i) {
-#pragma unroll
-                for (int q = 1; q < L::Q; ++q)
-                    if ((lk[i] >> q) & 1u)
-                        d[i][q] = Codec<ST>::dec(*at32(src + (size_t)L::opp[q] * g.stride, own + i), inv_scale);
-            }
-        }
-    }
-}
-
-template <int LAT, int V>
-__device__ __forceinline__ void load_links(const typename LinkMask<LAT>::T *links, int own,
-                                           typename LinkMask<LAT>::T (&lk)[V])
-{
-    using LT = typename LinkMask<LAT>::T;
-    if constexpr (V == 1) {
-        lk[0] = *at32(links, (unsigned)own);
-    } else {
-        typedef LT VT __attribute__((ext_vector_type(V)));
-        const VT v = *reinterpret_cast<const VT *>(at32(links, (unsigned)own));
-#pragma unroll
-        for (int i = 0; i < V; ++i) lk[i] = v[i];
-    }
-}
-
-// ---------------------------------------------------------------------------------
-// Collision of one node in deviation form: the discrete BGK update of Sec. 9.1 with the
-// reduced second-order EDF and the Lorentz source of Sec. 7, then the optional partial
-// bounce-back.
-//   rho = rho0 + drho, drho = sum d, j = sum d e, U = u / c_s = j / (rho c_s^2);
-//   deq_q = what_k drho + lam_k (e.j) + what_k rho (Bc (e.U)^2 + C_k c_s^2 U^2), q != 0,
-//           lam_k (e.j) = what_k rho A (e.U) with lam weights whose second moment is
-//           exactly the identity: the equilibrium carries exactly the node's momentum;
-//   deq_0 = drho - sum_(q != 0) deq_q (mass closure);
-//   sigma_q = (e.E / c_s)(A + 2 Bc e.U) + 2 C_k (c_s U.E + e.(B x U));
-//   d*_q = d_q + omega (deq_q - d_q) + rho what_k sigma_q;
-//   g_q = (1 - s) d*_q + s d_qbar.
-// FORCE: 0 no field, 1 E only, 2 E and B (source term); 3 velocity shift (E and B): no
-// sigma, and deq_q taken at j + rho tau c_s (E + u x B), i.e. at u + tau (E + u x B).
-// ---------------------------------------------------------------------------------
-template <int LAT>
-struct Macro {
-    float drho, rho, j[3], U[3], U2;
-};
-
-// Zeroth and first moments of the deviations: r = sum_q d_q, j = sum_q d_q e_q.
-template <int LAT>
-__device__ __forceinline__ void moment_sums(const float *d, float &r, float (&j)[3])
-{
-    using L = Lat<LAT>;
-    r = d[0];
-#pragma unroll
-    for (int q = 1; q < L::Q; ++q) r += d[q];
-    j[0] = j[1] = j[2] = 0.f;
-    bool fx = true, fy = true, fz = true;
-#pragma unroll
-    for (int q = 1; q < L::Q; ++q) {
-        if (L::ex[q]) {
-            const float t = L::ex[q] > 0 ? d[q] : -d[q];
-            j[0] = fx ? t : j[0] + t;
-            fx = false;
-        }
-        if (L::ey[q]) {
-            const float t = L::ey[q] > 0 ? d[q] : -d[q];
-            j[1] = fy ? t : j[1] + t;
-            fy = false;
-        }
-        if (L::ez[q]) {
-            const float t = L::ez[q] > 0 ? d[q] : -d[q];
-            j[2] = fz ? t : j[2] + t;
-            fz = false;
-        }
-    }
-}
-
-template <int LAT>
-__device__ __forceinline__ Macro<LAT> macro(const Physics &p, const float *d)
-{
-    using L = Lat<LAT>;
-    Macro<LAT> m;
-    float r, j[3];
-    moment_sums<LAT>(d, r, j);
-    m.drho = r;
-    m.rho = p.rho0 + r;
-    const float k = p.inv_cs2 * __builtin_amdgcn_rcpf(m.rho);
-    m.j[0] = j[0];
-    m.j[1] = j[1];
-    m.j[2] = j[2];
-    m.U[0] = j[0] * k;
-    m.U[1] = j[1] * k;
-    if constexpr (L::D == 3) {
-        m.U[2] = j[2] * k;
-        m.U2 = m.U[0] * m.U[0] + m.U[1] * m.U[1] + m.U[2] * m.U[2];
-    } else {
-        m.U[2] = 0.f;
-        m.U2 = m.U[0] * m.U[0] + m.U[1] * m.U[1];
-    }
-    return m;
-}
-
-// Forward collision of one node in stored units (deviations times the storage scale S):
-// BGK relaxation toward the reduced equilibrium plus the Lorentz source, with omega and S
-// folded into per-shell constants,
-//   o_q = (1 - omega) D_q + omega S deq_q + S w_q rho sigma_q
-//       = c0 D_q + ol_k (e_q.j) + owhat_k drho + whatS_k rho [omega Bc (e_q.U)^2
-//         + omega Cp_k U^2 + sigma_q],
-// sigma_q = (e_q.c1v) + c2q (e_q.U) + C2_k c_s (U.E) + C2_k e_q.(U x B). The rest population
-// follows from mass closure (relaxation and source conserve mass), o_0 = sum_q D_q -
-// sum_{q>0} o_q, which also keeps FP32 mass conservation exact up to one rounding per node.
-template <int LAT, int FORCE>
-__device__ __forceinline__ void relax_node(const Physics &p, const float *D, float *o)
-{
-    using L = Lat<LAT>;
-    float drho, j[3];  // stored units
-    moment_sums<LAT>(D, drho, j);
-    const float rho = __builtin_fmaf(drho, p.inv_scale, p.rho0);
-    const float kk = p.inv_cs2S * __builtin_amdgcn_rcpf(rho);
-    float U[3] = {j[0] * kk, j[1] * kk, L::D == 3 ? j[2] * kk : 0.f};
-    if constexpr (FORCE == 3) {
-        // velocity shift: the equilibrium takes u + tau (E + u x B), i.e. j + rho (shE +
-        // shB U x B); the relaxation then moves momentum by rho (E + u x B) per step
-        const float W[3] = {U[1] * p.B[2] - U[2] * p.B[1], U[2] * p.B[0] - U[0] * p.B[2],
-                            U[0] * p.B[1] - U[1] * p.B[0]};  // U x B
-#pragma unroll
-        for (int i = 0; i < L::D; ++i) {
-            j[i] = __builtin_fmaf(rho, __builtin_fmaf(p.shB, W[i], p.shE[i]), j[i]);
-            U[i] = j[i] * kk;
-        }
-    }
-    float U2 = U[0] * U[0] + U[1] * U[1];
-    if constexpr (L::D == 3) U2 = __builtin_fmaf(U[2], U[2], U2);
-    float wr[3], owd[3], P[3];
-#pragma unroll
-    for (int k = 1; k < 3; ++k) {
-        wr[k] = p.whatS[k] * rho;
-        owd[k] = p.owhat[k] * drho;
-        P[k] = p.oCp[k] * U2;
-    }
-    float H[3][3];
-    if constexpr (FORCE == 1 || FORCE == 2) {
-        float UE = U[0] * p.E[0] + U[1] * p.E[1];
-        if constexpr (L::D == 3) UE = __builtin_fmaf(U[2], p.E[2], UE);
-        UE *= p.cs;
-#pragma unroll
-        for (int k = 1; k < 3; ++k) P[k] = __builtin_fmaf(p.C2[k], UE, P[k]);
-    }
-    if constexpr (FORCE == 2) {
-        const float W[3] = {p.B[1] * U[2] - p.B[2] * U[1], p.B[2] * U[0] - p.B[0] * U[2],
-                            p.B[0] * U[1] - p.B[1] * U[0]};
-#pragma unroll
-        for (int k = 1; k < 3; ++k)
-#pragma unroll
-            for (int i = 0; i < 3; ++i) H[k][i] = __builtin_fmaf(p.C2[k], W[i], p.c1v[i]);
-    }
-    float sum = 0.f;
-    for_q<L::Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        if constexpr (q != 0) {
-            constexpr int k = shell<LAT, q>();
-            const float eu = edot<LAT, q>(U);
-            const float ej = edot<LAT, q>(j);
-            float inner;
-            if constexpr (FORCE == 0 || FORCE == 3)
-                inner = __builtin_fmaf(p.omBc * eu, eu, P[k]);
-            else if constexpr (FORCE == 1)
-                inner = __builtin_fmaf(__builtin_fmaf(p.omBc, eu, p.c2q[q]), eu, P[k] + p.c1q[q]);
-            else
-                inner = __builtin_fmaf(__builtin_fmaf(p.omBc, eu, p.c2q[q]), eu, P[k] + edot<LAT, q>(H[k]));
-            const float v = __builtin_fmaf(wr[k], inner,
-                                           __builtin_fmaf(p.ol[k], ej, __builtin_fmaf(p.c0, D[q], owd[k])));
-            o[q] = v;
-            sum = (q == 1) ? v : sum + v;
-        }
-    });
-    o[0] = drho - sum;
-}
-
-template <int LAT, bool SOFT, int FORCE>
-__device__ __forceinline__ void collide(const Physics &p, const float *D, float s, float *o)
-{
-    using L = Lat<LAT>;
-    relax_node<LAT, FORCE>(p, D, o);
-    if (SOFT) {
-        float t[L::Q];
-#pragma unroll
-        for (int q = 0; q < L::Q; ++q) t[q] = __builtin_fmaf(s, D[L::opp[q]] - o[q], o[q]);
-#pragma unroll
-        for (int q = 0; q < L::Q; ++q) o[q] = t[q];
-    }
-}
-
-// ---------------------------------------------------------------------------------
 // K1: fused pull-stream + collide + force + partial bounce-back.
 // ---------------------------------------------------------------------------------
 template <int LAT, int ST, bool MASK, bool SOFT, int FORCE, int V>
@@ -586,45 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, int ntx, FastDiv di
     float o[V][L::Q];
 #pragma unroll
     for (int i = 0; i < V; ++i) collide<LAT, SOFT, FORCE>(a.ph, d[i], SOFT ? sv[i] : 0.f, o[i]);
-    bool fluid[V];
-    bool all_fluid = true;
-    LT links = 0;  // union of the solid-neighbour bits of the fluid nodes
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-        fluid[i] = !MASK || !(lk[i] & LinkMask<LAT>::solid);
-        all_fluid = all_fluid && fluid[i];
-        if (MASK && fluid[i]) links |= lk[i];
-    }
-    T *__restrict__ dst = static_cast<T *>(a.dst);
-#pragma unroll
-    for (int q = 0; q < L::Q; ++q) {
-        T *p = at32(dst + (size_t)q * a.g.stride, (unsigned)t.own);
-        if (!MASK || all_fluid) {
-            float f[V];
-#pragma unroll
-            for (int i = 0; i < V; ++i) f[i] = o[i][q];
-            vstore<ST, V>(p, 1.f, f);
-        } else {
-#pragma unroll
-            for (int i = 0; i < V; ++i)
-                if (fluid[i]) *at32(p, (unsigned)i) = Codec<ST>::enc(o[i][q], 1.f);
-        }
-    }
-    if (MASK && kSolidSlotBB<ST> && links) {
-        // solid-slot bounce-back: where x - e_q is solid, the value the next step pulls
-        // into x as population q is f*_qbar(x); store it in slot q of that solid node
-        const PullRows r = pull_rows<V>(a.g, t);
-        for_q<L::Q>([&](auto qc) {
-            constexpr int q = decltype(qc)::value;
-            if constexpr (q != 0) {
-                T *row = dst + pull_row<LAT, q>(a.g, t, r);
-#pragma unroll
-                for (int i = 0; i < V; ++i)
-                    if (fluid[i] && ((lk[i] >> q) & 1u))
-                        *at32(row, pull_x<LAT, q, V>(r, i)) = Codec<ST>::enc(o[i][L::opp[q]], 1.f);
-            }
-        });
-    }
+    store_tile<LAT, ST, MASK, V>(a.g, static_cast<typename Codec<ST>::T *>(a.dst), t, lk, o);
 }
 
 // ---------------------------------------------------------------------------------
@@ -815,9 +270,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce_final(const double *__restric
 // ---------------------------------------------------------------------------------
 // K3/K4: gather kernels over the current state. MODE 0: rho and u fields; 1: FP64
 // export of the populations; 2: per-block FP64 partial sums
-// (sum drho, sum d e_x, sum d e_y, sum d e_z, fluid nodes).
+// (sum drho, sum d e_x, sum d e_y, sum d e_z, fluid nodes). ODD: the state is in the odd
+// layout of the in-place step (populations already streamed).
 // ---------------------------------------------------------------------------------
-template <int LAT, int ST, bool MASK, int MODE>
+template <int LAT, int ST, bool MASK, int MODE, bool ODD>
 __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
 {
     using L = Lat<LAT>;
@@ -825,6 +281,12 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
     using LT = typename LinkMask<LAT>::T;
     const T *src = static_cast<const T *>(a.src);
     const LT *links = static_cast<const LT *>(a.links);
+    auto pull = [&](const Tile &t, const LT *lk, float (&d)[1][L::Q]) {
+        if constexpr (ODD)
+            gather_odd<LAT, ST, MASK, 1>(a.g, src, a.ph.inv_scale, t, lk, d);
+        else
+            gather_tile<LAT, ST, MASK, 1>(a.g, src, a.ph.inv_scale, t, lk, d);
+    };
     if constexpr (MODE == 2) {
         double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         for (int b = blockIdx.x; b < a.g.nblocks; b += gridDim.x) {
@@ -836,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
                 if (lk[0] & LinkMask<LAT>::solid) continue;
             }
             float d[1][L::Q];
-            gather_tile<LAT, ST, MASK, 1>(a.g, src, a.ph.inv_scale, t, lk, d);
+            pull(t, lk, d);
             const Macro<LAT> m = macro<LAT>(a.ph, d[0]);
             acc[0] += m.drho;
             acc[1] += m.j[0];
@@ -855,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
             solid = (lk[0] & LinkMask<LAT>::solid) != 0;
         }
         float d[1][L::Q];
-        if (!solid) gather_tile<LAT, ST, MASK, 1>(a.g, src, a.ph.inv_scale, t, lk, d);
+        if (!solid) pull(t, lk, d);
         if constexpr (MODE == 0) {
             if (solid) {
                 if (a.rho) a.rho[t.own] = 0.f;
@@ -1145,12 +607,15 @@ hipError_t gather_lat_st(const GatherArgs &a, int nred, hipStream_t st)
     const dim3 block(kBlock);
     const int mode = a.partials ? 2 : (a.f64 ? 1 : 0);
     const dim3 grid(mode == 2 ? nred : a.g.nblocks);
-#define LBM_G(M, MODE) hipLaunchKernelGGL((k_gather<LAT, ST, M, MODE>), grid, block, 0, st, a)
-    if (mask) {
-        if (mode == 0) LBM_G(true, 0); else if (mode == 1) LBM_G(true, 1); else LBM_G(true, 2);
+#define LBM_G(M, MODE, O) hipLaunchKernelGGL((k_gather<LAT, ST, M, MODE, O>), grid, block, 0, st, a)
+#define LBM_G_MODE(M, O) \
+    if (mode == 0) LBM_G(M, 0, O); else if (mode == 1) LBM_G(M, 1, O); else LBM_G(M, 2, O)
+    if (a.odd) {
+        if (mask) LBM_G_MODE(true, true); else LBM_G_MODE(false, true);
     } else {
-        if (mode == 0) LBM_G(false, 0); else if (mode == 1) LBM_G(false, 1); else LBM_G(false, 2);
+        if (mask) LBM_G_MODE(true, false); else LBM_G_MODE(false, false);
     }
+#undef LBM_G_MODE
 #undef LBM_G
     return hipGetLastError();
 }

@@ -192,11 +192,13 @@ class Simulation:
 
     Geometry arrays: ``mask`` (uint8, 1 = solid) and ``s`` (partial bounce-back
     fraction in [0, 1]) of N nodes, numpy or torch; they are copied to the device once.
+    ``inplace=True`` binds one state buffer instead of two: the steps then update it in
+    place (the AA access pattern), with the same results and half the state memory.
     """
 
     def __init__(self, lattice="D2V9", nx=1, ny=1, nz=1, tau=0.8, E=(0.0, 0.0, 0.0), B=(0.0, 0.0, 0.0),
                  storage="f32", dev_scale_log2=0, rho0=1.0, stats="fd", theta=1.0 / 270.0, mu=1.0,
-                 mask=None, s=None, device="cuda", forcing="source", slip=0, work=None):
+                 mask=None, s=None, device="cuda", forcing="source", slip=0, work=None, inplace=False):
         import torch
 
         self.torch = torch
@@ -214,15 +216,18 @@ class Simulation:
         for name, arr in (("mask", self.mask), ("s", self.s)):
             if arr is not None and arr.numel() != self.N:
                 raise ValueError(f"{name} must have {self.N} entries")
-        self.bufs = [torch.zeros(self.sizes["state"], dtype=torch.uint8, device=self.device) for _ in range(2)]
+        self.inplace = bool(inplace)
+        self.bufs = [torch.zeros(self.sizes["state"], dtype=torch.uint8, device=self.device)
+                     for _ in range(1 if self.inplace else 2)]
         # workspace: the caller's (uint8 tensor of at least work bytes, any content) or zeros
         self.work = torch.zeros(self.sizes["work"], dtype=torch.uint8, device=self.device) if work is None else work
         if self.work.numel() < self.sizes["work"]:
             raise ValueError(f"work must hold {self.sizes['work']} bytes")
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
+        state_b = None if self.inplace else self.bufs[1]
         _check(self.lib.lbm_create(ctypes.byref(self.params), _ptr(self.mask), _ptr(self.s), _ptr(self.bufs[0]),
-                                   _ptr(self.bufs[1]), _ptr(self.work), ctypes.c_void_p(self.stream.cuda_stream),
+                                   _ptr(state_b), _ptr(self.work), ctypes.c_void_p(self.stream.cuda_stream),
                                    ctypes.byref(h)))
         self.h = h
         self.constants = compute_constants(lattice, stats, theta, mu)

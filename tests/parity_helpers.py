@@ -14,12 +14,12 @@ from oracle.oracle import OracleModel
 from paper_1710_09472_amd import workloads as W
 
 
-def gpu_sim(wl: W.Workload, storage="f32", dev_scale_log2=0, E=None, B=None):
+def gpu_sim(wl: W.Workload, storage="f32", dev_scale_log2=0, E=None, B=None, inplace=False):
     from paper_1710_09472_amd.lbm import Simulation
 
     sim = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E if E is None else E,
                      B=wl.B if B is None else B, storage=storage, dev_scale_log2=dev_scale_log2,
-                     mask=wl.mask, s=wl.s, forcing=wl.forcing, slip=wl.slip)
+                     mask=wl.mask, s=wl.s, forcing=wl.forcing, slip=wl.slip, inplace=inplace)
     sim.init(wl.rho, wl.u)
     return sim
 

@@ -152,6 +152,22 @@ def test_create_rejections_without_device_work():
     assert lib.lbm_status_string(lbm.LBM_ENONFINITE) == b"non-finite value in reduction"
 
 
+def test_inplace_create_without_device_work():
+    """state_b = NULL binds one state buffer (in-place steps); the same buffer passed
+    twice is refused. Without solids lbm_create does no device work."""
+    lib = lbm.load_library()
+    h = ctypes.c_void_p()
+    p = lbm.make_params("D2V9", 8, 8)
+    state, work = ctypes.c_void_p(4096), ctypes.c_void_p(1 << 20)
+    rc = lib.lbm_create(ctypes.byref(p), None, None, state, state, work, None, ctypes.byref(h))
+    assert rc == lbm.LBM_EINVAL and not h.value
+    rc = lib.lbm_create(ctypes.byref(p), None, None, None, None, work, None, ctypes.byref(h))
+    assert rc == lbm.LBM_EINVAL and not h.value
+    rc = lib.lbm_create(ctypes.byref(p), None, None, state, None, work, None, ctypes.byref(h))
+    assert rc == lbm.LBM_OK and h.value
+    lib.lbm_destroy(h)
+
+
 def test_buffer_sizes():
     s = lbm.buffer_sizes(lbm.make_params("D2V9", 4096, 4096))
     assert s["stride"] >= 4096 * 4096 and s["stride"] % 256 == 0 and s["state"] == 9 * s["stride"] * 4
