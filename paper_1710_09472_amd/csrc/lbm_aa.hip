@@ -26,9 +26,49 @@
 namespace lbm {
 namespace {
 
+// Store of an x-shifted population, 16-bit storage with two nodes per thread: the lane's
+// pair P = (g(x0), g(x0+1)) lands at x0 + 1, x0 + 2 (towards +x) or x0 - 1, x0 (towards
+// -x). Each lane joins the half of its neighbour lane's pair (DPP wave shift) that falls
+// in its own aligned pair of elements and stores both with one 32-bit store; the first
+// and last lanes of the wave (or of the row) store the half that falls in the
+// neighbouring wave's pair. Every lane of the wave up to the row's end must take part.
+// Two values encoded in 16 bits each, a in the low half (16-bit storage only).
+template <int ST>
+__device__ __forceinline__ uint32_t pack_pair(float a, float b)
+{
+    using T = typename Codec<ST>::T;
+    if constexpr (sizeof(T) == 2)
+        return (uint32_t)__builtin_bit_cast(uint16_t, Codec<ST>::enc(a, 1.f)) |
+               ((uint32_t)__builtin_bit_cast(uint16_t, Codec<ST>::enc(b, 1.f)) << 16);
+    else
+        return 0u;  // no pair stores with FP32 storage
+}
+
+template <int DIR>
+__device__ __forceinline__ void store_pair_shifted(uint16_t *row, const PullRows &r, uint32_t P, bool first, bool last)
+{
+    if constexpr (DIR > 0) {
+        const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)P, 0x138, 0xF, 0xF, false);  // wave_shr:1
+        if (!first)
+            __builtin_nontemporal_store(__builtin_amdgcn_alignbit(P, prev, 16), reinterpret_cast<uint32_t *>(at32(row, r.x0)));
+        else
+            __builtin_nontemporal_store((uint16_t)P, at32(row, r.x0 + 1u));
+        if (last) __builtin_nontemporal_store((uint16_t)(P >> 16), at32(row, r.xr));
+    } else {
+        const uint32_t next = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)P, 0x130, 0xF, 0xF, false);  // wave_shl:1
+        if (!last)
+            __builtin_nontemporal_store(__builtin_amdgcn_alignbit(next, P, 16), reinterpret_cast<uint32_t *>(at32(row, r.x0)));
+        else
+            __builtin_nontemporal_store((uint16_t)(P >> 16), at32(row, r.x0));
+        if (first) __builtin_nontemporal_store((uint16_t)P, at32(row, r.xl));
+    }
+}
+
 // Phase 0: pull, collide, store back where the opposite population was pulled from.
-// V nodes per thread as in the two-buffer step (same node arithmetic, same bits); the
-// stores of x-shifted populations are shifted like their loads, one value at a time.
+// V nodes per thread as in the two-buffer step (same node arithmetic, same bits). The
+// stores of x-shifted populations are shifted like their loads: one value at a time,
+// or, with 16-bit storage and two nodes per thread, as aligned pairs joined across
+// lanes.
 template <int LAT, int ST, bool MASK, bool SOFT, int FORCE, int V>
 __global__ __launch_bounds__(kBlock) void k_step_aa_pull(StepArgs a, int ntx, FastDiv div_ntx, int nblocks)
 {
@@ -38,6 +78,15 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_pull(StepArgs a, int ntx, Fa
     const int bid = a.remap ? xcd_remap((int)blockIdx.x, nblocks) : (int)blockIdx.x;
     const Tile t = tile_of<V>(a.g, bid, ntx, div_ntx);
     if (!t.valid) return;
+    // 16-bit storage, two nodes per thread: aligned pair stores joined across lanes, which
+    // need every lane of the wave. Obstacle nodes then take part like fluid ones: under
+    // the solid-slot convention the locations an obstacle node pulls from (and so stores
+    // to) are read and written by no fluid node. Nodes of free-slip wall planes are not
+    // like that, but they fill whole rows, so their waves leave as a whole. (Joining
+    // single values across lanes with one node per thread measured slower on MI355X than
+    // the shifted 16-bit stores.)
+    constexpr bool kPairs = ST != LBM_F32 && V == 2;
+    static_assert(!kPairs || kSolidSlotBB<ST>, "pair stores rely on the solid-slot convention");
     LT lk[V];
     bool fluid[V];
     bool all_fluid = true;
@@ -50,7 +99,11 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_pull(StepArgs a, int ntx, Fa
             any_fluid = any_fluid || fluid[i];
             all_fluid = all_fluid && fluid[i];
         }
-        if (!any_fluid) return;
+        if constexpr (kPairs) {
+            if (__builtin_amdgcn_ballot_w64(any_fluid) == 0) return;  // wave-uniform
+        } else {
+            if (!any_fluid) return;
+        }
     } else {
 #pragma unroll
         for (int i = 0; i < V; ++i) fluid[i] = true;
@@ -64,10 +117,24 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_pull(StepArgs a, int ntx, Fa
 #pragma unroll
     for (int i = 0; i < V; ++i) collide<LAT, SOFT, FORCE>(a.ph, d[i], SOFT ? sv[i] : 0.f, o[i]);
     const PullRows r = pull_rows<V>(a.g, t);
+    const unsigned lane = threadIdx.x & 63u;
+    const bool first = lane == 0, last = lane == 63 || t.x0 + V >= a.g.nx;
     for_q<L::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         constexpr int qb = L::opp[q];
         T *row = f + pull_row<LAT, qb>(a.g, t, r);  // P(x, qbar) without bounce-back
+        if constexpr (kPairs) {
+            if constexpr (L::ex[q] != 0) {
+                store_pair_shifted<L::ex[q]>(reinterpret_cast<uint16_t *>(row), r,
+                                             pack_pair<ST>(o[0][q], o[V - 1][q]), first, last);
+            } else {
+                float v[V];
+#pragma unroll
+                for (int i = 0; i < V; ++i) v[i] = o[i][q];
+                vstore<ST, V>(at32(row, r.x0), 1.f, v);
+            }
+            return;
+        }
         if constexpr (L::ex[q] == 0 && (!MASK || kSolidSlotBB<ST>)) {
             if (all_fluid) {
                 float v[V];

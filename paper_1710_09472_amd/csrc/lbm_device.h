@@ -348,36 +348,42 @@ __device__ __forceinline__ void gather_tile(const Geometry &g, const typename Co
 // Pre-collision deviations of the V nodes of tile t from a state in the odd layout of the
 // in-place step, where the pulled population f_q(x) sits in slot qbar of x itself, except
 // that with the solid-slot convention a bounced one stays where the pull reads it (slot q
-// of the solid node x - e_q).
+// of the solid node x - e_q). There every value is loaded once from a per-lane address
+// (own slot or solid slot), so that no load waits for another; 16-bit states are below
+// 4 GiB, so one 32-bit byte offset from src reaches every slot. Waves without a bounced
+// link load node pairs with vector loads.
 template <int LAT, int ST, bool MASK, int V>
 __device__ __forceinline__ void gather_odd(const Geometry &g, const typename Codec<ST>::T *src, float inv_scale,
                                            const Tile &t, const typename LinkMask<LAT>::T *lk,
                                            float (&d)[V][Lat<LAT>::Q])
 {
     using L = Lat<LAT>;
+    using LT = typename LinkMask<LAT>::T;
+    if constexpr (MASK && kSolidSlotBB<ST>) {
+        LT any = 0;
+#pragma unroll
+        for (int i = 0; i < V; ++i) any |= lk[i] & (LT)~LinkMask<LAT>::solid;
+        if (V == 1 || __builtin_amdgcn_ballot_w64(any != 0) != 0) {
+            const PullRows r = pull_rows<V>(g, t);
+            for_q<L::Q>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                const unsigned own = (unsigned)((size_t)L::opp[q] * g.stride) + (unsigned)t.own;
+                const unsigned row = (unsigned)pull_row<LAT, q>(g, t, r);
+#pragma unroll
+                for (int i = 0; i < V; ++i) {
+                    const unsigned off = (q != 0 && ((lk[i] >> q) & 1u)) ? row + pull_x<LAT, q, V>(r, i) : own + i;
+                    d[i][q] = Codec<ST>::dec(__builtin_nontemporal_load(at32(src, off)), inv_scale);
+                }
+            });
+            return;
+        }
+    }
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
         float f[V];
         vload<ST, V>(at32(src + (size_t)L::opp[q] * g.stride, (unsigned)t.own), inv_scale, f);
 #pragma unroll
         for (int i = 0; i < V; ++i) d[i][q] = f[i];
-    }
-    if constexpr (MASK && kSolidSlotBB<ST>) {
-        typename LinkMask<LAT>::T any = 0;
-#pragma unroll
-        for (int i = 0; i < V; ++i) any |= lk[i] & (typename LinkMask<LAT>::T)~LinkMask<LAT>::solid;
-        if (any) {
-            const PullRows r = pull_rows<V>(g, t);
-            for_q<L::Q>([&](auto qc) {
-                constexpr int q = decltype(qc)::value;
-                if constexpr (q != 0) {
-                    const typename Codec<ST>::T *row = src + pull_row<LAT, q>(g, t, r);
-#pragma unroll
-                    for (int i = 0; i < V; ++i)
-                        if ((lk[i] >> q) & 1u) d[i][q] = Codec<ST>::dec(*at32(row, pull_x<LAT, q, V>(r, i)), inv_scale);
-                }
-            });
-        }
     }
 }
 
