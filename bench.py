@@ -248,7 +248,7 @@ def cpu_baseline(wl, target_s: float = 12.0):
     periodic, with the same solids and porosity), scaled to MLUPS."""
     import numpy as np
 
-    from oracle.oracle import OracleModel, get_threads
+    from oracle.oracle import OracleModel, get_threads, set_threads
 
     nz = 1 if wl.nz == 1 else max(2, (1 << 19) // (wl.nx * wl.ny))
     ny = min(wl.ny, 256) if wl.nz == 1 else wl.ny
@@ -267,10 +267,29 @@ def cpu_baseline(wl, target_s: float = 12.0):
     dt = time.perf_counter() - t0
     assert np.isfinite(f).all()
     mlups = n * steps / dt / 1e6
+    cores = get_threads()
+    # the same oracle on one thread, over a shorter window
+    set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        f = m.run(f, 1, mask=mask, s=s)
+        one1 = time.perf_counter() - t0
+        steps1 = max(1, int(target_s / 3 / max(one1, 1e-4)))
+        t0 = time.perf_counter()
+        f = m.run(f, steps1, mask=mask, s=s)
+        mlups1 = n * steps1 / (time.perf_counter() - t0) / 1e6
+    finally:
+        set_threads(cores)
+    model = ""
+    try:
+        model = next(ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     dims = f"{wl.nx}x{ny}" + (f"x{nz}" if wl.nz > 1 else "")
     full = f"{wl.nx}x{wl.ny}" + (f"x{wl.nz}" if wl.nz > 1 else "")
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": get_threads(), "kind": "oracle",
-            "sample": f"{wl.lattice} {dims} slab of the {full} grid, FP64, {steps} steps in {dt:.1f} s"}
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{wl.lattice} {dims} slab of the {full} grid, FP64, {steps} steps in {dt:.1f} s",
+            "single_thread_value": round(mlups1, 3), "cpu_model": model}
 
 
 def main():
