@@ -17,10 +17,12 @@ definitions:
   finding (Sec. 9.1-9.2: rho = (pi theta)^(D/2) g_(D/2)(e^(mu/theta)));
 * weight integrals I_2N: eq. (i2n-cont2) of Sec. 3 (radial form);
 * polynomial coefficients c_K, c'_K, cbar_K, Delta_2K, J_2K: the coefficient list
-  of Sec. 3 (K <= 2 only; the second-order model of Sec. 9 needs nothing higher);
+  of Sec. 3 (K <= 2 for the second-order model of Sec. 9; the whole list to K = 4,
+  d_4, d'_4 and dbar_4 included, for the fourth-order thermal model);
 * pseudo-temperature thetabar = I_2/I_0: Sec. 9.1;
 * reference speed c_s and weights w_alpha of D2V9, D3V15, D3V19, D3V27: Sec. 8 and
-  Table 1 (lattices-tab).
+  Table 1 (lattices-tab); D1V7: App. A (quadrature equations to order 9, their printed
+  solution, and the printed closed-form root of the c_s equation).
 
 No blocking, caching trick or reformulation is applied beyond what those formulas say.
 """
@@ -35,6 +37,9 @@ mp.mp.dps = 40
 
 #: Lattices whose weights Table 1 gives in closed form in terms of I_0, I_2, I_4 (, I_6).
 LATTICE_DIM = {"D2V9": 2, "D3V15": 3, "D3V19": 3, "D3V27": 3}
+
+#: D1V7 (App. A): e = 0, +1, -1, +2, -2, +3, -3 in the paper's order.
+D1V7_E = (0, 1, -1, 2, -2, 3, -3)
 
 
 def _omega(stats: str, theta, mu, D: int):
@@ -225,3 +230,71 @@ def mu_from_density(D: int, rho, stats: str = "fd", theta="1/270") -> mp.mpf:
         while g(a) > 0:
             a *= 2
     return mp.findroot(g, (a, b), solver="illinois", tol=mp.mpf(10) ** -32, maxsteps=400, verify=False)
+
+
+@dataclass(frozen=True)
+class Coefficients4:
+    """The coefficient list of Sec. 3 up to K = 4 (14 coefficients) and the I_2N used."""
+
+    D: int
+    I: dict          # {2N: I_2N}, N = 0..5
+    c: dict          # c_K, K = 0..4
+    cp: dict         # c'_K, K = 2..4
+    cbar: dict       # cbar_K, K = 2..4
+    d4: mp.mpf
+    d4p: mp.mpf
+    d4bar: mp.mpf
+
+
+@functools.lru_cache(maxsize=None)
+def coefficients4(D: int, stats: str = "fd", theta="1/270", mu=1.0) -> Coefficients4:
+    """Coefficient list of Sec. 3 to K = 4:
+
+        c_K = I_2K^(-1/2)                                     (K = 0..4)
+        c'_K = -c_K (I_(2K-2) / I_(2K-4)) Delta_(2K-2)          (K = 2..4)
+        cbar_K = c_K (-1 + Delta_(2K-2)) / (D + 2K - 4)         (K = 2..4)
+        Delta_2K = sqrt(2 / ((D + 2K) - J_2K (D + 2K - 2))),  J_2K = I_2K^2 / (I_(2K+2) I_(2K-2))
+        d_4^2 = 8 delta_4^2 I_4 / (delta_2 [delta_2 delta_6 (D + 4) - delta_4^2 D])
+        d'_4 = -(d_4 / D) [I_0/I_2 + I_4 delta_2 / (I_2 delta_4)] + 2 c_4 I_6 Delta_6 / (D I_4)
+        dbar_4 = d_4 delta_2 / (D (D+2) delta_4) + c_4 [D - 2 (D+2) Delta_6] / (D (D+2) (D+4))
+        delta_L = 2 I_(L+2) I_(L-2) / Delta_L^2   (Delta_L = Delta_2K for L = 2K).
+    The positive root is taken for d_4. Reading: Delta_L with an even index L stands for the
+    Delta_2K of the same index, the only one defined."""
+    I = {2 * n: weight_integral(D, 2 * n, stats, theta, mu) for n in range(6)}
+    c = {K: 1 / mp.sqrt(I[2 * K]) for K in range(5)}
+    J = lambda K: I[2 * K] ** 2 / (I[2 * K + 2] * I[2 * K - 2])
+    Dl = lambda K: mp.sqrt(2 / ((D + 2 * K) - J(K) * (D + 2 * K - 2)))  # Delta_2K
+    cp = {K: -c[K] * I[2 * K - 2] / I[2 * K - 4] * Dl(K - 1) for K in (2, 3, 4)}
+    cbar = {K: c[K] * (-1 + Dl(K - 1)) / (D + 2 * K - 4) for K in (2, 3, 4)}
+    dl = lambda L: 2 * I[L + 2] * I[L - 2] / Dl(L // 2) ** 2
+    d4 = mp.sqrt(8 * dl(4) ** 2 * I[4] / (dl(2) * (dl(2) * dl(6) * (D + 4) - dl(4) ** 2 * D)))
+    d4p = -d4 / D * (I[0] / I[2] + I[4] * dl(2) / (I[2] * dl(4))) + 2 * c[4] * I[6] * Dl(3) / (D * I[4])
+    d4bar = d4 * dl(2) / (D * (D + 2) * dl(4)) + c[4] * (D - 2 * (D + 2) * Dl(3)) / (D * (D + 2) * (D + 4))
+    return Coefficients4(D, I, c, cp, cbar, d4, d4p, d4bar)
+
+
+@functools.lru_cache(maxsize=None)
+def d1v7(stats: str = "fd", theta="1/270", mu=1.0) -> dict:
+    """D1V7 of App. A: c_s from the printed closed form (principal branches of the square
+    and cube roots; the real part is kept, the imaginary part is rounding), one of the
+    positive roots of 12 I_2 - 49 I_4 c_s^2 + 70 I_6 c_s^4 - 35 I_8 c_s^6 = 0, and the
+    printed solution of the quadrature equations for w_0..w_3 (weights of |e| = 0..3).
+    The I_2N are those of eq. (i2n-cont2) with D = 1.
+
+    Returns {"cs", "w": {0: w_0, 1: w_1, 2: w_2, 3: w_3}, "I": {2N: I_2N}} (mpf)."""
+    I = {2 * n: weight_integral(1, 2 * n, stats, theta, mu) for n in range(5)}
+    I2, I4, I6, I8 = I[2], I[4], I[6], I[8]
+    A = -4900 * I6 ** 2 + 5145 * I4 * I8
+    B = 686000 * I6 ** 3 - 1080450 * I4 * I6 * I8 + 396900 * I2 * I8 ** 2
+    R = mp.cbrt(B + mp.sqrt(mp.mpc(4 * A ** 3 + B ** 2)))
+    c2 = 2 * I6 / (3 * I8) - 49 * mp.cbrt(2) * I4 / R + 140 * mp.cbrt(2) * I6 ** 2 / (3 * I8 * R) \
+        + R / (105 * mp.cbrt(2) * I8)
+    cs = mp.re(mp.sqrt(c2))
+    y = cs ** 2
+    w = {
+        0: (360 * I[0] - 150 * I6 * y ** 3 + 420 * I4 * y ** 2 - 490 * I2 * y) / 360,
+        1: (-13 * I4 * y ** 2 + 5 * I6 * y ** 3 + 12 * I2 * y) / 16,
+        2: (30 * I4 * y ** 2 - 15 * I6 * y ** 3 - 9 * I2 * y) / 120,
+        3: (15 * I6 * y ** 3 - 15 * I4 * y ** 2 + 4 * I2 * y) / 720,
+    }
+    return {"cs": cs, "w": w, "I": I}

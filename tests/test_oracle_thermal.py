@@ -1,0 +1,315 @@
+"""Pins of the fourth-order thermal oracle (oracle/thermal.py) and of the constants it
+uses (oracle/constants.py: coefficients4, d1v7), against what the paper and the
+mathematics fix:
+
+* D1V7 (App. A): the quadrature equations to order 9, the printed weights as the solution
+  of those equations, the printed c_s as a root of the printed cubic (the largest one;
+  all weights positive) for the electron weight, a moderately degenerate one and a near
+  Boltzmann one.
+* The coefficient list of Sec. 3 to K = 4 (the d_4 family included): orthonormality of
+  the polynomials, eq. (omeg-feq), by direct quadrature in 1D and, tensor by tensor, in
+  2D; the Hermite limit printed in Sec. 3 (c_K = 1, cbar_K = 0, c'_K = -1, d_4 = 1,
+  dbar_4 = d'_4 = 0).
+* Fermi-Dirac relations: rho, thetabar, g from polylogarithms equal the weight integrals
+  of the same distribution; g -> 1 (Boltzmann) and g -> 3/5 (ground state).
+* The equilibrium: its moments to order 4; the weight's own state maps to the weight;
+  it equals the paper's expansion sum (1/N!) A_N P_N with A_N integrated from the
+  Fermi-Dirac distribution (the definition of eq. feq-complete-exp-eq); with the Hermite
+  weight it is the textbook fourth-order Hermite expansion of a Maxwellian.
+* The step: conservation of mass, momentum and the second moment; the weight's state is a
+  fixed point; the slow thermal mode decays at the rate of the paper's energy equation
+  (eq. energy-cons-eq with the heat flux eq. pseudo-heat-flux-eq) in lattice units, in
+  the Boltzmann limit and in the degenerate regime; the stability statement of the
+  g-held reading.
+"""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from oracle import constants as C
+from oracle import thermal as T
+
+SETS = [("fd", "1/270", 1.0), ("fd", 0.25, 1.0), ("fd", 1.0, -5.0)]
+
+
+@pytest.mark.parametrize("stats,theta,mu", SETS)
+def test_d1v7_quadrature_equations(stats, theta, mu):
+    k = C.d1v7(stats, theta, mu)
+    cs, w, I = k["cs"], k["w"], k["I"]
+    e = C.D1V7_E
+    wa = [w[abs(a)] for a in e]
+    for n in range(5):
+        lhs = mp.fsum(wv * mp.mpf(a) ** (2 * n) for wv, a in zip(wa, e))
+        rhs = mp.mpf(math.prod(range(2 * n - 1, 0, -2))) * I[2 * n] * cs ** (2 * n)
+        assert abs(lhs - rhs) <= mp.mpf(10) ** -25 * abs(rhs), n
+    for n in range(5):  # odd moments vanish
+        assert abs(mp.fsum(wv * mp.mpf(a) ** (2 * n + 1) for wv, a in zip(wa, e))) < mp.mpf(10) ** -30
+    assert all(v > 0 for v in w.values())
+    y = cs ** 2
+    cubic = 12 * I[2] - 49 * I[4] * y + 70 * I[6] * y ** 2 - 35 * I[8] * y ** 3
+    assert abs(cubic) < mp.mpf(10) ** -25
+    roots = [mp.re(r) for r in mp.polyroots([-35 * I[8], 70 * I[6], -49 * I[4], 12 * I[2]])
+             if abs(mp.im(r)) < 1e-20 and mp.re(r) > 0]
+    assert abs(y - max(roots)) < mp.mpf(10) ** -20
+
+
+@pytest.mark.parametrize("stats,theta,mu", SETS[:2])
+def test_d1v7_printed_weights_solve_the_equations(stats, theta, mu):
+    k = C.d1v7(stats, theta, mu)
+    cs, I = k["cs"], k["I"]
+    # unknowns (w0, w1, w2, w3), rows: sum w e^2n = (2n-1)!! I_2n cs^2n, n = 0..3
+    A = mp.matrix([[1, 2, 2, 2], [0, 2, 8, 18], [0, 2, 32, 162], [0, 2, 128, 1458]])
+    b = mp.matrix([I[0], I[2] * cs ** 2, 3 * I[4] * cs ** 4, 15 * I[6] * cs ** 6])
+    sol = mp.lu_solve(A, b)
+    for i in range(4):
+        assert abs(sol[i] - k["w"][i]) < mp.mpf(10) ** -25 * abs(sol[i])
+
+
+def _poly1d(k):
+    """The N = 0..4 polynomials of Sec. 3 with every index 1 (delta_11 = 1; the fully
+    symmetric fourth-order delta is 3 in one dimension)."""
+    c, cp, cb = k.c, k.cp, k.cbar
+    return [lambda x: c[0] + 0 * x,
+            lambda x: c[1] * x,
+            lambda x: c[2] * x ** 2 + (cb[2] * x ** 2 + cp[2]),
+            lambda x: c[3] * x ** 3 + 3 * (cb[3] * x ** 2 + cp[3]) * x,
+            lambda x: c[4] * x ** 4 + 6 * (cb[4] * x ** 2 + cp[4]) * x ** 2
+            + 3 * (k.d4bar * x ** 4 + k.d4p * x ** 2 + k.d4)]
+
+
+@pytest.mark.parametrize("theta,mu", [(0.25, 1.0), (1.0, -5.0)])
+def test_polynomials_to_fourth_order_orthonormal_1d(theta, mu):
+    k = C.coefficients4(1, "fd", theta, mu)
+    P = _poly1d(k)
+    th, m = mp.mpf(theta), mp.mpf(mu)
+    w = lambda x: 1 / (mp.exp((x * x - m) / th) + 1)
+    pts = sorted({mp.mpf(0)} | {mp.sqrt(m + j * th) for j in range(-8, 60) if m + j * th > 0})
+    for N in range(5):
+        for M in range(N % 2, 5, 2):  # odd products integrate to zero by parity
+            h = lambda x: w(x) * P[N](x) * P[M](x)
+            val = 2 * (mp.quad(h, pts) + mp.quad(h, [pts[-1], mp.inf]))
+            want = math.factorial(N) if N == M else 0
+            assert abs(val - want) < mp.mpf(10) ** -20, (N, M, val)
+
+
+def _gl(a, b, n=48):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (b - a) * x + 0.5 * (b + a), 0.5 * (b - a) * w
+
+
+def _tensor(k, idx, X):
+    """P_idx at points X (2, npts) in 2D, from the general form of Sec. 3."""
+    N = len(idx)
+    x2 = (X ** 2).sum(0)
+    d = lambda i, j: 1.0 if i == j else 0.0
+    xi = lambda i: X[i]
+    f = lambda K: float(k.cbar[K]) * x2 + float(k.cp[K])
+    c = {K: float(v) for K, v in k.c.items()}
+    if N == 0:
+        return c[0] + 0 * x2
+    if N == 1:
+        return c[1] * xi(idx[0])
+    if N == 2:
+        i, j = idx
+        return c[2] * xi(i) * xi(j) + f(2) * d(i, j)
+    if N == 3:
+        i, j, l = idx
+        return c[3] * xi(i) * xi(j) * xi(l) + f(3) * (xi(i) * d(j, l) + xi(j) * d(i, l) + xi(l) * d(i, j))
+    i, j, l, m = idx
+    g4 = float(k.d4bar) * x2 ** 2 + float(k.d4p) * x2 + float(k.d4)
+    pairs = xi(i) * xi(j) * d(l, m) + xi(i) * xi(l) * d(j, m) + xi(i) * xi(m) * d(j, l) \
+        + xi(j) * xi(l) * d(i, m) + xi(j) * xi(m) * d(i, l) + xi(l) * xi(m) * d(i, j)
+    return c[4] * xi(i) * xi(j) * xi(l) * xi(m) + f(4) * pairs + g4 * (d(i, j) * d(l, m) + d(i, l) * d(j, m)
+                                                                         + d(i, m) * d(j, l))
+
+
+def _perm_count(a, b):
+    import itertools
+
+    return sum(all(a[k] == b[s[k]] for k in range(len(a))) for s in itertools.permutations(range(len(b))))
+
+
+def test_polynomials_orthonormal_2d_tensors():
+    """eq. (omeg-feq) in 2D for every pair of components of order <= 4 (FD weight,
+    theta = 1/4, mu = 1), by polar quadrature (Gauss-Legendre panels in r across the
+    Fermi edge, 64 equally spaced angles: exact for the trigonometric polynomials here)."""
+    k = C.coefficients4(2, "fd", 0.25, 1.0)
+    edges = [0, 0.4, 0.7, 0.85, 0.95, 1.0, 1.05, 1.15, 1.3, 1.6, 2.0, 2.6, 3.4, 4.5]
+    r, wr = np.concatenate([_gl(a, b)[0] for a, b in zip(edges[:-1], edges[1:])]), \
+        np.concatenate([_gl(a, b)[1] for a, b in zip(edges[:-1], edges[1:])])
+    phi = 2 * np.pi * np.arange(64) / 64
+    R, PH = np.meshgrid(r, phi, indexing="ij")
+    X = np.stack([(R * np.cos(PH)).ravel(), (R * np.sin(PH)).ravel()])
+    W = (wr[:, None] * R * (2 * np.pi / 64)).ravel() / (np.exp((R.ravel() ** 2 - 1.0) / 0.25) + 1)
+    comps = [(), (0,), (1,), (0, 0), (0, 1), (1, 1), (0, 0, 0), (0, 0, 1), (0, 1, 1), (0, 0, 0, 0), (0, 0, 0, 1),
+             (0, 0, 1, 1), (0, 1, 1, 1), (1, 1, 1, 1)]
+    vals = {c: _tensor(k, c, X) for c in comps}
+    for a in comps:
+        for b in comps:
+            got = float((W * vals[a] * vals[b]).sum())
+            want = _perm_count(a, b) if len(a) == len(b) else 0
+            assert abs(got - want) < 1e-10 * max(1, want), (a, b, got, want)
+
+
+def test_hermite_limit_of_the_coefficients():
+    for D in (1, 2, 3):
+        k = C.coefficients4(D, "hermite")
+        for K in range(5):
+            assert abs(k.c[K] - 1) < 1e-25
+        for K in (2, 3, 4):
+            assert abs(k.cbar[K]) < 1e-25 and abs(k.cp[K] + 1) < 1e-25
+        assert abs(k.d4 - 1) < 1e-25 and abs(k.d4bar) < 1e-25 and abs(k.d4p) < 1e-25
+
+
+@pytest.mark.parametrize("theta,mu", [(0.25, 1.0), (1.0, -5.0)])
+def test_fd_relations_match_weight_integrals(theta, mu):
+    rho, tb, g = T.fd_state(mp.mpf(mu) / theta, theta)
+    I = {2 * n: C.weight_integral(1, 2 * n, "fd", theta, mu) for n in range(3)}
+    assert abs(rho - I[0]) < mp.mpf(10) ** -20 * I[0]
+    assert abs(tb - I[2] / I[0]) < mp.mpf(10) ** -20
+    assert abs(g - I[4] * I[0] / I[2] ** 2) < mp.mpf(10) ** -20
+
+
+def test_g_limits():
+    assert abs(T.g_of_s(1e-10) - 1) < 1e-4          # Boltzmann
+    _, _, g = T.fd_state(400, 1)                    # deep in the ground state
+    assert abs(g - mp.mpf(3) / 5) < 1e-4
+
+
+def test_state_table_against_root_finding():
+    m = T.ThermalOracle(4, 0.8, g_mode="state")
+    tab = T._table(*m.x_range)
+    for s in (m.s_ref, 9.0, 10.9):
+        assert abs(float(tab(s)) - float(T.g_of_s(s))) < 1e-13
+
+
+@pytest.fixture(scope="module")
+def oracle():
+    return T.ThermalOracle(32, 0.8)
+
+
+def test_equilibrium_moments_and_reference(oracle):
+    m = oracle
+    rng = np.random.default_rng(3)
+    n = 50
+    rho = m.rho_ref * (1 + 0.05 * rng.uniform(-1, 1, n))
+    u = 0.05 * rng.uniform(-1, 1, n)
+    tb = m.thetabar_ref * (1 + 0.05 * rng.uniform(-1, 1, n))
+    g = m.g_ref * (1 + 0.05 * rng.uniform(-1, 1, n))
+    feq = m.equilibrium(rho, u, tb, g)
+    M = m.moments_target(rho, u, tb, g)
+    for kk in range(5):
+        got = (feq * m.xi[:, None] ** kk).sum(0)
+        np.testing.assert_allclose(got, M[kk], rtol=1e-12, atol=1e-13)
+    ref = m.equilibrium(np.array([m.rho_ref]), np.zeros(1), np.array([m.thetabar_ref]), np.array([m.g_ref]))
+    np.testing.assert_allclose(ref[:, 0], m.w, rtol=1e-13)
+
+
+def test_equilibrium_is_the_papers_projection():
+    """omega p(xi) = omega sum_N (1/N!) A_N P_N(xi), A_N = int f^FD P_N, for a moving
+    Fermi-Dirac state (z = e^3.6, theta = 0.3, u = 0.07) under the theta = 1/4, mu = 1
+    weight, with the polynomials of the Sec. 3 coefficient list."""
+    theta_w, mu_w = 0.25, 1.0
+    m = T.ThermalOracle(4, 0.8, theta=theta_w, mu=mu_w)
+    k = C.coefficients4(1, "fd", theta_w, mu_w)
+    P = _poly1d(k)
+    x, th, u = mp.mpf("3.6"), mp.mpf("0.3"), mp.mpf("0.07")
+    fFD = lambda v: 1 / (mp.exp((v - u) ** 2 / th - x) + 1)
+    pts = sorted({u + s * mp.sqrt(th * (x + j)) for s in (-1, 1) for j in (-3, 0, 4, 12)})
+    A = [mp.quad(lambda v: fFD(v) * P[N](v), [-mp.inf] + pts + [mp.inf]) for N in range(5)]
+    rho, tb, g = T.fd_state(x, th)
+    # the moment solve in FP64 with this state's rho, u, thetabar, g
+    c = np.linalg.solve(m.H, m.moments_target(np.array([float(rho)]), np.array([float(u)]),
+                                              np.array([float(tb)]), np.array([float(g)])))[:, 0]
+    for v in (-1.3, -0.6, 0.0, 0.45, 1.1):
+        paper = mp.fsum(A[N] * P[N](mp.mpf(v)) / math.factorial(N) for N in range(5))
+        mine = sum(c[j] * v ** j for j in range(5))
+        assert abs(float(paper) - mine) < 1e-11 * max(1.0, abs(mine)), (v, float(paper), mine)
+
+
+def test_hermite_weight_gives_the_hermite_expansion():
+    """Hermite weight, Maxwellian state (g = 1): p = rho sum_n (1/n!) a_n He_n(xi) with
+    a_1 = u, a_2 = u^2 + t, a_3 = u^3 + 3 u t, a_4 = u^4 + 6 u^2 t + 3 t^2, t = thetabar - 1."""
+    m = T.ThermalOracle(4, 0.8, stats="hermite")
+    rho, u, tb = 1.3, 0.17, 0.86
+    feq = m.equilibrium(np.array([rho]), np.array([u]), np.array([tb]), np.array([1.0]))[:, 0]
+    t = tb - 1
+    a = [1, u, u * u + t, u ** 3 + 3 * u * t, u ** 4 + 6 * u * u * t + 3 * t * t]
+    He = lambda n, v: [1, v, v * v - 1, v ** 3 - 3 * v, v ** 4 - 6 * v * v + 3][n]
+    for i, v in enumerate(m.xi):
+        want = m.w[i] * rho * sum(a[n] * He(n, v) / math.factorial(n) for n in range(5))
+        assert abs(feq[i] - want) < 1e-13, (i, feq[i], want)
+
+
+def test_step_conserves_and_reference_is_fixed(oracle):
+    m = oracle
+    rng = np.random.default_rng(4)
+    N = m.N
+    f = m.init_state(m.rho_ref * (1 + 0.02 * rng.uniform(-1, 1, N)), 0.02 * rng.uniform(-1, 1, N),
+                     m.thetabar_ref * (1 + 0.02 * rng.uniform(-1, 1, N)))
+    t0 = m.totals(f)
+    f1 = m.run(f, 10)
+    t1 = m.totals(f1)
+    for a, b in zip(t0, t1):
+        assert abs(a - b) < 1e-12 * max(1.0, abs(a))
+    ref = m.init_state(np.full(N, m.rho_ref), np.zeros(N), np.full(N, m.thetabar_ref))
+    np.testing.assert_allclose(m.step(ref), ref, rtol=0, atol=1e-15)
+
+
+def _linear_modes(rho, th, g0, tau, k):
+    """Linearised 1D equations of Sec. 6 (no shear stress in 1D) around rest: continuity,
+    momentum with p = rho thetabar, energy with eq. (pseudo-heat-flux-eq) and g held at
+    g0; state (drho, u, dthetabar), all in lattice units."""
+    tp = tau - 0.5
+    kap = 1.5 * rho * th * tp
+    dkt = lambda: 1.5 * tp  # d(kappa thetabar) = 1.5 tp (th^2 drho + 2 rho th dth)
+    A = np.array([[0, -1j * k * rho, 0],
+                  [-1j * k * th / rho, 0, -1j * k],
+                  [-(2 / rho) * (g0 - 1) * k * k * dkt() * th * th, -2j * k * th,
+                   -(2 / rho) * (k * k * kap + (g0 - 1) * k * k * dkt() * 2 * rho * th)]])
+    return np.linalg.eig(A)
+
+
+@pytest.mark.parametrize("theta,mu", [(1.0, -5.0), (0.25, 1.0)])
+def test_thermal_mode_decays_as_the_energy_equation(theta, mu):
+    N, tau = 64, 0.8
+    m = T.ThermalOracle(N, tau, theta=theta, mu=mu)
+    k = 2 * np.pi / N
+    ev, vec = _linear_modes(m.rho_ref, m.thetabar_ref * m.cs ** 2, m.g_ref, tau, k)
+    i = int(np.argmin(np.abs(ev.imag)))  # the non-propagating (thermal) mode
+    left = np.linalg.inv(vec)[i]
+    x = np.arange(N)
+    tb = m.thetabar_ref * (1 + 1e-4 * np.sin(k * x))
+    f = m.init_state(m.rho_ref * m.thetabar_ref / tb, np.zeros(N), tb)
+    ts, amp = [], []
+    for t in range(801):
+        if t % 10 == 0 and t >= 200:
+            r, u, b = m.macro(f)
+            F = lambda q: np.fft.fft(q)[1] / N
+            amp.append(abs(left @ np.array([F(r - m.rho_ref), F(u * m.cs), F((b - m.thetabar_ref) * m.cs ** 2)])))
+            ts.append(t)
+        f = m.step(f)
+    rate = -np.polyfit(ts, np.log(amp), 1)[0]
+    assert abs(rate / -ev[i].real - 1) < 5e-3, (rate, -ev[i].real)
+
+
+def _amplification(m, N=16):
+    f0 = m.init_state(np.full(N, m.rho_ref), np.zeros(N), np.full(N, m.thetabar_ref))
+    n, h = f0.size, 1e-7
+    J = np.zeros((n, n))
+    for i in range(n):
+        d = np.zeros(n)
+        d[i] = h
+        J[:, i] = (m.step(f0 + d.reshape(f0.shape)) - m.step(f0 - d.reshape(f0.shape))).ravel() / (2 * h)
+    return np.abs(np.linalg.eigvals(J)).max()
+
+
+def test_stability_of_the_g_held_reading():
+    """Linear amplification per step around rest (16 nodes, finite-difference Jacobian):
+    with g held the D1V7 step is stable in the degenerate and the Boltzmann regimes; with
+    g following the local state it is unstable in the degenerate one."""
+    for theta, mu in ((0.25, 1.0), (1.0, -5.0)):
+        assert _amplification(T.ThermalOracle(16, 0.8, theta=theta, mu=mu)) < 1 + 1e-6
+    assert _amplification(T.ThermalOracle(16, 0.8, theta=0.25, mu=1.0, g_mode="state")) > 1.01
