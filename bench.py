@@ -59,12 +59,20 @@ WORKLOAD_DESC = {
                     "velocity-shift forcing E_x=1e-7, tau=0.9",
     "poiseuille_paper_2d": "poiseuille_paper_2d: D2V9 256x256, bounce-back rows y=0,255, velocity-shift forcing "
                            "E_x=1e-8, tau=0.8",
+    "thermal_1d": "thermal_1d: D1V7 2^24 nodes periodic, fourth-order thermal model, Fermi-Dirac weight "
+                  "theta=1/4 mu=1, rho=1+0.01N(0,1), u=0.01N(0,1), thetabar=thetabar_ref(1+0.01N(0,1)) seed 6, "
+                  "tau=0.8",
 }
 
 
 def make_workload(name: str):
     from paper_1710_09472_amd import workloads as W
 
+    if name == "thermal_1d":
+        from paper_1710_09472_amd import lbm
+
+        k = lbm.compute_constants("D1V7", "fd", 0.25, 1.0)
+        return W.thermal_1d(k["I2"] / k["I0"])
     return {"throughput_2d": W.throughput_2d, "hall_duct_3d": W.hall_duct_3d,
             "porous_ohm_2d": W.porous_ohm_2d, "soft_porous_3d": W.soft_porous_3d,
             "ohm_paper_2d": W.ohm_paper_2d, "ohm_paper_3d": W.ohm_paper_3d,
@@ -213,13 +221,14 @@ def adjoint_pipeline():
             "ratio_to_forward": round(bwd / fwd, 3), "dJ_dEx": float(gE[0]), "dJ_dtau": float(gT)}
 
 
-def kernel_code_hash() -> str:
-    """sha256 of the step kernel's sources (the device header and the kernel file) without
-    // comments and blank lines: it changes with the code, not with its comments."""
+def kernel_code_hash(thermal: bool = False) -> str:
+    """sha256 of a step kernel's sources (the device header and the kernel file: the
+    isothermal step's or the thermal step's) without // comments and blank lines: it
+    changes with the code, not with its comments."""
     import hashlib
 
     lines = []
-    for name in ("lbm_device.h", "lbm_kernels.hip"):
+    for name in ("lbm_device.h", "lbm_thermal.hip" if thermal else "lbm_kernels.hip"):
         for line in (ROOT / "paper_1710_09472_amd" / "csrc" / name).read_text().splitlines():
             line = re.sub(r"//.*$", "", line).rstrip()
             if line.strip():
@@ -237,9 +246,35 @@ def traffic_from_profile(kernel_tag: str):
     txt = f.read_text()
     m = re.search(r"^hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt, re.M)
     h = re.search(r"^kernel_code_sha256:\s*([0-9a-f]+)", txt, re.M)
-    if not m or not h or kernel_code_hash() != h.group(1):
+    if not m or not h or kernel_code_hash(kernel_tag.startswith("k_thermal")) != h.group(1):
         return None
     return float(m.group(1))
+
+
+def cpu_baseline_thermal(wl, target_s: float = 12.0):
+    """The FP64 thermal oracle (numpy) on the first 2^20 nodes of the 1D workload
+    (periodic), scaled to MLUPS; numpy uses one thread for these element-wise passes."""
+    from oracle.thermal import ThermalOracle
+
+    n = min(wl.N, 1 << 20)
+    m = ThermalOracle(n, wl.tau, theta=wl.theta, mu=wl.mu)
+    f = m.init_state(wl.rho[:n], wl.u[0, :n], wl.thetabar[:n])
+    f = m.step(f)
+    t0 = time.perf_counter()
+    f = m.step(f)
+    one = time.perf_counter() - t0
+    steps = max(1, int(target_s / max(one, 1e-4)))
+    t0 = time.perf_counter()
+    f = m.run(f, steps)
+    dt = time.perf_counter() - t0
+    model = ""
+    try:
+        model = next(ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    return {"value": round(n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"D1V7 first {n} nodes of the {wl.N}-node grid (periodic), FP64 numpy, {steps} steps in "
+                      f"{dt:.1f} s", "cpu_model": model}
 
 
 def cpu_baseline(wl, target_s: float = 12.0):
@@ -249,6 +284,9 @@ def cpu_baseline(wl, target_s: float = 12.0):
     import numpy as np
 
     from oracle.oracle import OracleModel, get_threads, set_threads
+
+    if wl.lattice == "D1V7":
+        return cpu_baseline_thermal(wl, target_s)
 
     nz = 1 if wl.nz == 1 else max(2, (1 << 19) // (wl.nx * wl.ny))
     ny = min(wl.ny, 256) if wl.nz == 1 else wl.ny
@@ -328,16 +366,23 @@ def main():
     st = args.storage
     elem = 4 if st == "f32" else 2
     k16 = F16_SCALE[args.workload] if st == "f16" else 0
+    thermal = wl.lattice == "D1V7"
+    if thermal and (st != "f32" or args.inplace):
+        sys.exit("thermal_1d: FP32 storage and two state buffers only")
     sim = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E, B=wl.B, storage=st,
                      dev_scale_log2=k16, mask=wl.mask, s=wl.s, forcing=wl.forcing, slip=wl.slip,
-                     inplace=args.inplace)
-    sim.init(wl.rho, wl.u)
+                     inplace=args.inplace, theta=wl.theta, mu=wl.mu)
+    if thermal:
+        sim.init(wl.rho, wl.u, wl.thetabar)
+    else:
+        sim.init(wl.rho, wl.u)
     wall, ev = timed_steps(sim, args.steps, args.warmup)
     t_launch = ev / args.steps
     mlups = N * args.steps / wall / 1e6
     alg = algorithmic_bytes(wl, sim.Q, elem)
     achieved = alg / t_launch / 1e9
-    traffic = None if args.inplace else traffic_from_profile(f"k_step_{wl.lattice}_{st}_{args.workload}")
+    traffic = None if args.inplace else traffic_from_profile(
+        f"{'k_thermal_step' if thermal else 'k_step'}_{wl.lattice}_{st}_{args.workload}")
     tot = sim.current()
     sim.close()
     del sim
@@ -363,7 +408,8 @@ def main():
         extras["inplace"] = {"f32": inplace_extra(wl, "f32", 0, args.steps, args.warmup),
                              "f16": inplace_extra(wl, "f16", F16_SCALE["throughput_2d"], args.steps, args.warmup)}
 
-    kernel = ("k_step_aa_pull+k_step_aa_local" if args.inplace else "k_step") + \
+    kernel = ("k_thermal_step" if thermal else
+              "k_step_aa_pull+k_step_aa_local" if args.inplace else "k_step") + \
         f"<{wl.lattice},{st.upper()}" + (",mask" if wl.mask is not None else "") + \
         (",slip" if wl.slip else "") + (",soft" if wl.s is not None else "") + \
         (",shift" if wl.forcing == "shift" else "") + ">"

@@ -36,9 +36,12 @@ extern "C" {
 
 typedef struct lbm_s *lbm_t;
 
-/* Lattices (Sec. 8, Table 1). D3V15 is listed only so that it can be rejected: under
- * the electron weight its rest weight is negative, which Sec. 8 forbids. */
-enum { LBM_D2V9 = 0, LBM_D3V19 = 1, LBM_D3V15 = 2 };
+/* Lattices (Sec. 8, Table 1, App. A). D3V15 is listed only so that it can be rejected:
+ * under the electron weight its rest weight is negative, which Sec. 8 forbids.
+ * LBM_D1V7 (App. A, e = 0, +-1, +-2, +-3, quadrature of order 9) carries the
+ * fourth-order thermal model: the equilibrium expanded to K = 4 (Sec. 3-6), periodic
+ * in x (ny = nz = 1), FP32 storage, no fields, solids or porosity; see lbm_init_thermal. */
+enum { LBM_D2V9 = 0, LBM_D3V19 = 1, LBM_D3V15 = 2, LBM_D1V7 = 3 };
 
 /* Weight functions: the Fermi-Dirac electron weight 1/(exp((xi^2 - mu)/theta) + 1) of
  * eq. (weight-func-isotherm-eq), Sec. 9.1; the Bose-Einstein weight
@@ -79,10 +82,10 @@ enum { LBM_FORCE_SOURCE = 0, LBM_FORCE_SHIFT = 1 };
 enum { LBM_SLIP_Y = 1, LBM_SLIP_Z = 2 };
 
 typedef struct {
-    int lattice;        /* LBM_D2V9 or LBM_D3V19 */
+    int lattice;        /* LBM_D2V9, LBM_D3V19, or LBM_D1V7 (thermal model) */
     int stats;          /* LBM_FERMI_DIRAC or LBM_HERMITE */
     int storage;        /* LBM_F32, LBM_F16 or LBM_BF16 */
-    int nx, ny, nz;     /* grid; nz = 1 for D2V9; each >= 1, nx*ny*nz*Q < 2^31 */
+    int nx, ny, nz;     /* grid; nz = 1 for D2V9, ny = nz = 1 for D1V7; each >= 1, nx*ny*nz*Q < 2^31 */
     double theta, mu;   /* weight parameters (electron model: 1/270 and 1) */
     double tau;         /* BGK relaxation time in steps, > 1/2 */
     double E[3];        /* electric acceleration, xi-units per step */
@@ -154,6 +157,22 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *s
  * ...), xi-units, or NULL for u = 0. Values at solid nodes are ignored. Async. */
 int lbm_init(lbm_t h, const double *rho, const double *u);
 
+/* Initial state of the fourth-order thermal model (LBM_D1V7 only, LBM_EUNSUPPORTED
+ * otherwise): f_a(x) = f^eq_a(rho(x), u(x), thetabar(x)), the equilibrium expanded to
+ * K = 4 in the polynomials orthonormal under the weight (eq. feq-complete-exp-eq,
+ * Sec. 3-5), i.e. w_a p(xi_a) with the polynomial p of degree 4 whose moments on the
+ * lattice are those of the local distribution, M_0..M_4 = rho, rho u, rho (thetabar + u^2),
+ * rho (u^3 + 3 u thetabar), rho (u^4 + 6 u^2 thetabar + 3 thetabar^2 g) (eqs. rho-def-eq,
+ * vel-def-eq, theta-bar-def-eq, gz-def-eq). g is held at the weight's own value
+ * I_4 I_0 / I_2^2, as Sec. 9.1 holds thetabar for the isothermal model (a g that follows
+ * the local state makes the model unstable in the degenerate regime). rho: device
+ * double[N]; u, thetabar: device double[N] or NULL (0, and the weight's I_2/I_0). The
+ * lattice moves e = 0, +-1, +-2, +-3 per step; xi = e / c_s with the c_s of App. A.
+ * lbm_step then relaxes to this equilibrium (BGK) and streams, periodic in x; the
+ * energy equation of Sec. 6 follows, with the heat flux of eq. (pseudo-heat-flux-eq).
+ * Async. */
+int lbm_init_thermal(lbm_t h, const double *rho, const double *u, const double *thetabar);
+
 /* Advance nsteps >= 0 time steps (collide, force, partial bounce-back, stream,
  * halfway bounce-back and free-slip walls: the discrete BGK update of Sec. 9.1 with
  * the forcing of Sec. 7). With one state buffer (state_b = NULL) the steps alternate
@@ -169,6 +188,14 @@ int lbm_step_from(lbm_t h, const void *src, void *dst);
 /* Fields of the current state (pre-collision): rho (device float[N]) and u (device
  * float[D*N] SoA, xi-units). Solid nodes get 0. Either pointer may be NULL. Async. */
 int lbm_moments(lbm_t h, float *rho, float *u);
+
+/* Thermal model (LBM_D1V7) only: thetabar of the current state, device float[N], defined
+ * by rho (thetabar + u^2) = sum_a f_a xi_a^2 (eq. theta-bar-def-eq). Async. */
+int lbm_thetabar(lbm_t h, float *thetabar);
+
+/* Thermal model (LBM_D1V7) only: sum over nodes of sum_a f_a xi_a^2 (twice the kinetic
+ * energy, conserved by the collision), FP64 into host *out. Synchronises the stream. */
+int lbm_energy(lbm_t h, double *out);
 
 /* Totals over fluid nodes of the current state, accumulated in FP64:
  * out[0] = sum rho, out[1..3] = sum rho u (xi-units; out[3] = 0 in 2D). out is host

@@ -1,7 +1,8 @@
 """Build the HIP library ``liblbm_hip.so`` in-tree for gfx950.
 
 Sources: ``csrc/lbm_kernels.hip`` (device kernels and launchers; device helpers in
-``csrc/lbm_device.h``), ``csrc/lbm_aa.hip`` (the in-place step), ``csrc/lbm_density.hip``
+``csrc/lbm_device.h``), ``csrc/lbm_aa.hip`` (the in-place step), ``csrc/lbm_thermal.hip``
+(the fourth-order thermal model on D1V7), ``csrc/lbm_density.hip``
 (rho <-> mu), ``csrc/lbm_capi.cpp`` (the C ABI of ``include/lbm.h``) and
 ``csrc/lbm_consts.cpp`` (host FP64 constants).
 Every source goes through hipcc with packed-FP32 instruction selection disabled.
@@ -21,7 +22,7 @@ CSRC = PKG / "csrc"
 INCLUDE = ROOT / "include"
 BUILD = PKG / "_build"
 LIB = PKG / "liblbm_hip.so"
-SOURCES = ["lbm_kernels.hip", "lbm_aa.hip", "lbm_density.hip", "lbm_capi.cpp", "lbm_consts.cpp"]
+SOURCES = ["lbm_kernels.hip", "lbm_aa.hip", "lbm_thermal.hip", "lbm_density.hip", "lbm_capi.cpp", "lbm_consts.cpp"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 

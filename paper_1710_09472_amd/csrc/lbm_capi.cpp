@@ -46,6 +46,8 @@ struct lbm_s {
     void *links = nullptr;  // per-node link masks inside the work buffer
     bool initialized = false;
     bool adj_held = false;  // work_adj holds adjoint contributions not yet reduced
+    bool thermal = false;   // D1V7: the fourth-order thermal model
+    ThermalPhysics tph{};
     std::string err;
 };
 
@@ -90,8 +92,15 @@ int lattice_dims(int lattice, int *Q, int *D)
         *D = 3;
         return LBM_OK;
     }
+    if (lattice == LBM_D1V7) {
+        *Q = 7;
+        *D = 1;
+        return LBM_OK;
+    }
     return LBM_EINVAL;
 }
+
+constexpr int kD1V7E[7] = {0, 1, -1, 2, -2, 3, -3};
 
 size_t elem_size(int storage) { return storage == LBM_F32 ? 4 : 2; }
 
@@ -131,6 +140,14 @@ int validate(const lbm_params *p, lbm_t h, Sizes *sz)
         return fail(h, LBM_EINVAL, "unknown storage %d", p->storage);
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(h, LBM_EINVAL, "grid sizes must be >= 1");
     if (D == 2 && p->nz != 1) return fail(h, LBM_EINVAL, "D2V9 needs nz = 1");
+    if (D == 1) {
+        if (p->ny != 1 || p->nz != 1) return fail(h, LBM_EINVAL, "D1V7 needs ny = nz = 1");
+        for (int i = 0; i < 3; ++i)
+            if (p->E[i] != 0.0 || p->B[i] != 0.0) return fail(h, LBM_EINVAL, "D1V7 (thermal model): no E or B");
+        if (p->slip) return fail(h, LBM_EINVAL, "D1V7 (thermal model): no free-slip walls");
+        if (p->storage != LBM_F32)
+            return fail(h, LBM_EUNSUPPORTED, "D1V7 (thermal model): FP32 storage only");
+    }
     const double N = (double)p->nx * p->ny * p->nz;
     const double stride = std::ceil(N / 256.0) * 256.0 + stride_pad();
     if (stride * Q >= 2147483647.0) return fail(h, LBM_EINVAL, "grid too large (Q * N must stay below 2^31)");
@@ -261,7 +278,61 @@ int force_level(const lbm_t h)
 // link masks exist where there are solids: obstacles of the mask, or slip wall planes
 bool has_solids(const lbm_t h) { return h->mask != nullptr || h->p.slip != 0; }
 const void *links_of(const lbm_t h) { return has_solids(h) ? h->links : nullptr; }
-bool adjoint_supported(const lbm_t h) { return h->p.forcing == LBM_FORCE_SOURCE && h->p.slip == 0; }
+bool adjoint_supported(const lbm_t h) { return h->p.forcing == LBM_FORCE_SOURCE && h->p.slip == 0 && !h->thermal; }
+
+// Constants of the thermal kernel (D1V7) from the weights: what, xi, the weight's
+// thetabar and g, and the inverses of the even and odd blocks of the Hankel matrix of the
+// what moments, m_k = sum_a what_a xi_a^k (equal to the weight's moments up to order 9).
+void fill_thermal(lbm_t h)
+{
+    ThermalPhysics &t = h->tph;
+    t = ThermalPhysics{};
+    const lbm_constants &k = h->k;
+    t.omega = (float)(1.0 / h->p.tau);
+    t.rho0 = (float)h->p.rho0;
+    long double what[7], m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // e-moments sum what e^j
+    for (int a = 0; a < 7; ++a) {
+        what[a] = (long double)k.w[std::abs(kD1V7E[a])] / (long double)k.I0;
+        t.what[a] = (float)what[a];
+        t.what_rho0[a] = (double)(what[a] * (long double)h->p.rho0);
+        long double pw = 1.0L;
+        for (int j = 0; j < 9; ++j) {
+            m[j] += what[a] * pw;
+            pw *= kD1V7E[a];
+        }
+    }
+    t.T = (double)m[2];
+    t.tb_hi = (float)m[2];
+    t.tb_lo = (float)(m[2] - (long double)t.tb_hi);
+    t.cs = k.cs;
+    t.g0 = (float)(m[4] / (3.0L * m[2] * m[2]));  // I_4 I_0 / I_2^2 (the same in any unit of velocity)
+    // even block over (0, 2, 4): E[i][j] = m[2i + 2j]; odd block over (1, 3): m[2i + 2j + 2]
+    const long double E[3][3] = {{m[0], m[2], m[4]}, {m[2], m[4], m[6]}, {m[4], m[6], m[8]}};
+    const long double det = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
+                            E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+                            E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            // inverse = adjugate / det; adj[i][j] = cofactor of E[j][i]
+            const int r0 = (j + 1) % 3, r1 = (j + 2) % 3, c0 = (i + 1) % 3, c1 = (i + 2) % 3;
+            t.He_inv[3 * i + j] = (float)((E[r0][c0] * E[r1][c1] - E[r0][c1] * E[r1][c0]) / det);
+        }
+    const long double O[2][2] = {{m[2], m[4]}, {m[4], m[6]}};
+    const long double dO = O[0][0] * O[1][1] - O[0][1] * O[1][0];
+    t.Ho_inv[0] = (float)(O[1][1] / dO);
+    t.Ho_inv[1] = (float)(-O[0][1] / dO);
+    t.Ho_inv[2] = (float)(-O[1][0] / dO);
+    t.Ho_inv[3] = (float)(O[0][0] / dO);
+}
+
+ThermalArgs thermal_args(const lbm_t h)
+{
+    ThermalArgs a{};
+    a.n = h->N;
+    a.stride = h->stride;
+    a.ph = h->tph;
+    return a;
+}
 
 double *work_out(lbm_t h) { return reinterpret_cast<double *>(h->work); }
 double *work_parts(lbm_t h) { return reinterpret_cast<double *>(h->work + work_layout(h->g.nblocks, h->stride).parts); }
@@ -306,7 +377,11 @@ int lbm_lattice_info(int lattice, int *Q, int *D, int *e)
     if (D) *D = d;
     if (e) {
         for (int a = 0; a < q; ++a) {
-            if (lattice == LBM_D2V9) {
+            if (lattice == LBM_D1V7) {
+                e[3 * a] = kD1V7E[a];
+                e[3 * a + 1] = 0;
+                e[3 * a + 2] = 0;
+            } else if (lattice == LBM_D2V9) {
                 e[3 * a] = Lat<LBM_D2V9>::ex[a];
                 e[3 * a + 1] = Lat<LBM_D2V9>::ey[a];
                 e[3 * a + 2] = 0;
@@ -349,6 +424,10 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *s
     }
     if (!state_a || !work) return fail(nullptr, LBM_EINVAL, "state_a and work are required");
     if (state_a == state_b) return fail(nullptr, LBM_EINVAL, "state_a and state_b must be distinct buffers");
+    if (p->lattice == LBM_D1V7) {
+        if (mask || s) return fail(nullptr, LBM_EUNSUPPORTED, "D1V7 (thermal model): no solids or porosity");
+        if (!state_b) return fail(nullptr, LBM_EUNSUPPORTED, "D1V7 (thermal model): two state buffers needed");
+    }
     lbm_s *h = new (std::nothrow) lbm_s;
     if (!h) return fail(nullptr, LBM_EDEVICE, "out of host memory");
     h->p = *p;
@@ -380,7 +459,11 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *s
     h->g.mask = mask;
     h->g.s = s;
     h->g.slip = p->slip;
-    fill_physics(h);
+    h->thermal = p->lattice == LBM_D1V7;
+    if (h->thermal)
+        fill_thermal(h);
+    else
+        fill_physics(h);
     h->links = work_links(h);
     if (has_solids(h)) {
         const hipError_t e = launch_links(p->lattice, h->g, h->links, h->stream);
@@ -401,6 +484,7 @@ int density_common(const lbm_params *p, const double *in, double *out, size_t n,
     if (!p) return fail(nullptr, LBM_EINVAL, "null params");
     int Q, D;
     if (lattice_dims(p->lattice, &Q, &D) != LBM_OK) return fail(nullptr, LBM_EINVAL, "unknown lattice %d", p->lattice);
+    if (D == 1) return fail(nullptr, LBM_EUNSUPPORTED, "rho(mu) is provided in 2D and 3D");
     if (p->stats != LBM_FERMI_DIRAC && p->stats != LBM_BOSE_EINSTEIN)
         return fail(nullptr, LBM_EINVAL, "rho(mu) needs the Fermi-Dirac or Bose-Einstein weight");
     if (!(p->theta > 0) || !std::isfinite(p->theta)) return fail(nullptr, LBM_EINVAL, "theta must be finite and > 0");
@@ -421,10 +505,28 @@ int lbm_mu_from_density(const lbm_params *p, const double *rho, double *mu, size
     return density_common(p, rho, mu, n, stream, true);
 }
 
+int lbm_init_thermal(lbm_t h, const double *rho, const double *u, const double *thetabar)
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    if (!h->thermal) return fail(h, LBM_EUNSUPPORTED, "lbm_init_thermal needs the D1V7 thermal model");
+    if (!rho) return fail(h, LBM_EINVAL, "rho is required");
+    ThermalArgs a = thermal_args(h);
+    a.rho = rho;
+    a.u = u;
+    a.tb = thetabar;
+    a.dst = static_cast<float *>(h->buf[h->cur]);
+    const hipError_t e = launch_thermal(1, a, 0, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "thermal init kernel launch");
+    h->initialized = true;
+    h->parity = 0;
+    return LBM_OK;
+}
+
 int lbm_init(lbm_t h, const double *rho, const double *u)
 {
     if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
     if (!rho) return fail(h, LBM_EINVAL, "rho is required");
+    if (h->thermal) return lbm_init_thermal(h, rho, u, nullptr);
     InitArgs a{};
     a.g = h->g;
     a.ph = h->ph;
@@ -449,6 +551,17 @@ int lbm_step(lbm_t h, int nsteps)
     a.ph = h->ph;
     a.links = links_of(h);
     a.remap = use_xcd_remap(h->p.lattice, has_solids(h), h->s != nullptr);
+    if (h->thermal) {
+        ThermalArgs ta = thermal_args(h);
+        for (int t = 0; t < nsteps; ++t) {
+            ta.src = static_cast<const float *>(h->buf[h->cur]);
+            ta.dst = static_cast<float *>(h->buf[h->cur ^ 1]);
+            const hipError_t e = launch_thermal(0, ta, 0, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "thermal step kernel launch");
+            h->cur ^= 1;
+        }
+        return LBM_OK;
+    }
     const int force = force_level(h);
     if (h->aa) {
         a.src = a.dst = h->buf[0];
@@ -473,6 +586,14 @@ int lbm_step_from(lbm_t h, const void *src, void *dst)
 {
     if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
     if (!src || !dst || src == dst) return fail(h, LBM_EINVAL, "src and dst must be distinct non-null buffers");
+    if (h->thermal) {
+        ThermalArgs ta = thermal_args(h);
+        ta.src = static_cast<const float *>(src);
+        ta.dst = static_cast<float *>(dst);
+        const hipError_t e = launch_thermal(0, ta, 0, h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "thermal step kernel launch");
+        return LBM_OK;
+    }
     StepArgs a{};
     a.g = h->g;
     a.ph = h->ph;
@@ -485,8 +606,35 @@ int lbm_step_from(lbm_t h, const void *src, void *dst)
     return LBM_OK;
 }
 
+static int thermal_gather(lbm_t h, const void *state, float *rho, float *u, float *tb, double *f64, double *parts)
+{
+    ThermalArgs a = thermal_args(h);
+    a.src = static_cast<const float *>(state ? state : h->buf[h->cur]);
+    a.out_rho = rho;
+    a.out_u = u;
+    a.out_tb = tb;
+    a.f64 = f64;
+    a.partials = parts;
+    const hipError_t e = launch_thermal(parts ? 4 : (f64 ? 3 : 2), a, kReduceBlocks, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "thermal gather kernel launch");
+    return LBM_OK;
+}
+
+// Reduce the thermal per-block partials (already in work_parts) to (sum drho, sum j, sum dE).
+static int thermal_totals(lbm_t h, double tot[3])
+{
+    hipError_t e = launch_reduce_final(work_parts(h), kReduceBlocks, 3, work_out(h), 0, h->stream, work_stage(h));
+    if (e != hipSuccess) return hip_fail(h, e, "reduce kernel launch");
+    e = hipMemcpyAsync(tot, work_out(h), 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "copy of totals");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "stream synchronize");
+    return LBM_OK;
+}
+
 static int gather_common(lbm_t h, const void *state, float *rho, float *u, double *f64, double *parts)
 {
+    if (h->thermal) return thermal_gather(h, state, rho, u, nullptr, f64, parts);
     GatherArgs a{};
     a.g = h->g;
     a.ph = h->ph;
@@ -512,6 +660,32 @@ int lbm_moments(lbm_t h, float *rho, float *u)
     return gather_common(h, nullptr, rho, u, nullptr, nullptr);
 }
 
+int lbm_thetabar(lbm_t h, float *thetabar)
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    if (!h->thermal) return fail(h, LBM_EUNSUPPORTED, "thetabar is a field of the D1V7 thermal model");
+    if (!thetabar) return fail(h, LBM_EINVAL, "thetabar is required");
+    if (!h->initialized) return fail(h, LBM_ESTATE, "lbm_thetabar before lbm_init or lbm_set_state");
+    return thermal_gather(h, nullptr, nullptr, nullptr, thetabar, nullptr, nullptr);
+}
+
+int lbm_energy(lbm_t h, double *out)
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    if (!h->thermal) return fail(h, LBM_EUNSUPPORTED, "lbm_energy is a total of the D1V7 thermal model");
+    if (!out) return fail(h, LBM_EINVAL, "out is required");
+    if (!h->initialized) return fail(h, LBM_ESTATE, "lbm_energy before lbm_init or lbm_set_state");
+    int rc = thermal_gather(h, nullptr, nullptr, nullptr, nullptr, nullptr, work_parts(h));
+    if (rc != LBM_OK) return rc;
+    double tot[3];
+    rc = thermal_totals(h, tot);
+    if (rc != LBM_OK) return rc;
+    // sum over nodes of sum_a f xi^2; the weight's state contributes rho0 I_2 / I_0 per node
+    *out = (double)h->N * h->p.rho0 * (h->k.I2 / h->k.I0) + tot[2] / (h->tph.cs * h->tph.cs);
+    if (!std::isfinite(*out)) return fail(h, LBM_ENONFINITE, "non-finite energy total");
+    return LBM_OK;
+}
+
 int lbm_export_f64(lbm_t h, const void *state, double *dst)
 {
     if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
@@ -527,6 +701,17 @@ int lbm_current(lbm_t h, double out[4])
     if (!h->initialized) return fail(h, LBM_ESTATE, "lbm_current before lbm_init or lbm_set_state");
     int rc = gather_common(h, nullptr, nullptr, nullptr, nullptr, work_parts(h));
     if (rc != LBM_OK) return rc;
+    if (h->thermal) {
+        double tot[3];
+        rc = thermal_totals(h, tot);
+        if (rc != LBM_OK) return rc;
+        out[0] = (double)h->N * h->p.rho0 + tot[0];
+        out[1] = tot[1] / h->tph.cs;  // lattice units to xi
+        out[2] = out[3] = 0.0;
+        for (int i = 0; i < 2; ++i)
+            if (!std::isfinite(out[i])) return fail(h, LBM_ENONFINITE, "non-finite total (component %d)", i);
+        return LBM_OK;
+    }
     hipError_t e = launch_reduce_final(work_parts(h), kReduceBlocks, 5, work_out(h), 0, h->stream, work_stage(h));
     if (e != hipSuccess) return hip_fail(h, e, "reduce kernel launch");
     double tot[5];
@@ -588,7 +773,10 @@ int lbm_set_fields(lbm_t h, const double E[3], const double B[3])
     const int rc = validate(&q, h, nullptr);
     if (rc != LBM_OK) return rc;
     h->p = q;
-    fill_physics(h);
+    if (h->thermal)
+        fill_thermal(h);
+    else
+        fill_physics(h);
     return LBM_OK;
 }
 
@@ -600,7 +788,10 @@ int lbm_set_tau(lbm_t h, double tau)
     const int rc = validate(&q, h, nullptr);
     if (rc != LBM_OK) return rc;
     h->p = q;
-    fill_physics(h);
+    if (h->thermal)
+        fill_thermal(h);
+    else
+        fill_physics(h);
     return LBM_OK;
 }
 

@@ -2,11 +2,13 @@
 //
 // Weight integrals I_2N of eq. (i2n-cont2) (Sec. 3) by composite Gauss-Legendre
 // quadrature on panels finer than the width of the Fermi edge; polynomial coefficients
-// of Sec. 3 (K <= 2); reference speed and weights of Sec. 8 / Table 1; the reduced
-// equilibrium of Sec. 9.1 collapsed to what_a [1 + A (xi.u) + Bc (xi.u)^2 + C_k u^2].
+// of Sec. 3 (K <= 2); reference speed and weights of Sec. 8 / Table 1 and of D1V7
+// (App. A); the reduced equilibrium of Sec. 9.1 collapsed to
+// what_a [1 + A (xi.u) + Bc (xi.u)^2 + C_k u^2].
 #include "lbm_internal.h"
 
 #include <cmath>
+#include <complex>
 #include <vector>
 
 namespace lbm {
@@ -58,9 +60,15 @@ long double omega(int stats, long double xi, long double theta, long double mu, 
 // I_2N for N = 0..3 (out[0..3] = I_0, I_2, I_4, I_6).
 int weight_integrals(int stats, int D, double theta, double mu, double out[4])
 {
-    if (!(D == 2 || D == 3)) return LBM_EINVAL;
+    return weight_integrals_n(stats, D, theta, mu, 4, out);
+}
+
+// I_2N for N = 0..n-1 (n <= 5; out[N] = I_2N), D = 1, 2 or 3.
+int weight_integrals_n(int stats, int D, double theta, double mu, int n, double *out)
+{
+    if (!(D >= 1 && D <= 3) || n < 1 || n > 5) return LBM_EINVAL;
     if (stats == LBM_HERMITE) {
-        for (int i = 0; i < 4; ++i) out[i] = 1.0;  // exact for the Hermite weight, Sec. 3
+        for (int i = 0; i < n; ++i) out[i] = 1.0;  // exact for the Hermite weight, Sec. 3
         // (kept analytic; the quadrature path is used for every other weight)
         return LBM_OK;
     }
@@ -79,28 +87,78 @@ int weight_integrals(int stats, int D, double theta, double mu, double out[4])
     const int npan = (int)std::ceil(xmax / h);
     std::vector<long double> gx, gw;
     gauss_legendre(10, gx, gw);
-    long double acc[4] = {0, 0, 0, 0};
+    long double acc[5] = {0, 0, 0, 0, 0};
     for (int p = 0; p < npan; ++p) {
         const long double a = p * (xmax / npan), b = (p + 1) * (xmax / npan);
         const long double c = 0.5L * (a + b), r = 0.5L * (b - a);
         for (size_t k = 0; k < gx.size(); ++k) {
             const long double xi = c + r * gx[k];
             const long double wk = r * gw[k] * omega(stats, xi, th, m, D);
-            long double pw = std::pow(xi, (long double)(D - 1));
-            for (int N = 0; N < 4; ++N) {
+            long double pw = D == 1 ? 1.0L : std::pow(xi, (long double)(D - 1));
+            for (int N = 0; N < n; ++N) {
                 acc[N] += wk * pw;
                 pw *= xi * xi;
             }
         }
     }
-    for (int N = 0; N < 4; ++N)
+    for (int N = 0; N < n; ++N)
         out[N] = (double)(std::pow((long double)M_PI, 0.5L * D) /
                           (std::pow(2.0L, (long double)(N - 1)) * std::tgamma(N + 0.5L * D)) * acc[N]);
     return LBM_OK;
 }
 
+// D1V7 (App. A): c_s from the printed closed form of the root of
+// 12 I_2 - 49 I_4 c^2 + 70 I_6 c^4 - 35 I_8 c^6 = 0 (principal square and cube roots, in
+// complex arithmetic; the result is real up to rounding), then the printed solution
+// w_0..w_3 of the quadrature equations (weights of |e| = 0..3).
+int d1v7_constants(const double I[5], double *cs_out, double w[4])
+{
+    using C = std::complex<long double>;
+    const long double I0 = I[0], I2 = I[1], I4 = I[2], I6 = I[3], I8 = I[4];
+    const long double A = -4900.0L * I6 * I6 + 5145.0L * I4 * I8;
+    const long double B = 686000.0L * I6 * I6 * I6 - 1080450.0L * I4 * I6 * I8 + 396900.0L * I2 * I8 * I8;
+    const C R = std::pow(C(B) + std::sqrt(C(4.0L * A * A * A + B * B)), 1.0L / 3.0L);
+    const long double c2r = std::cbrt(2.0L);
+    const C c2 = C(2.0L * I6 / (3.0L * I8)) - 49.0L * c2r * I4 / R + 140.0L * c2r * I6 * I6 / (3.0L * I8 * R) +
+                 R / (105.0L * c2r * I8);
+    if (!(c2.real() > 0) || std::fabs(c2.imag()) > 1e-9L * c2.real()) return LBM_EUNSUPPORTED;
+    const long double y = c2.real();
+    const long double cubic = 12.0L * I2 - 49.0L * I4 * y + 70.0L * I6 * y * y - 35.0L * I8 * y * y * y;
+    if (!(std::fabs(cubic) <= 1e-9L * 12.0L * I2)) return LBM_EUNSUPPORTED;
+    w[0] = (double)((360.0L * I0 - 150.0L * I6 * y * y * y + 420.0L * I4 * y * y - 490.0L * I2 * y) / 360.0L);
+    w[1] = (double)((-13.0L * I4 * y * y + 5.0L * I6 * y * y * y + 12.0L * I2 * y) / 16.0L);
+    w[2] = (double)((30.0L * I4 * y * y - 15.0L * I6 * y * y * y - 9.0L * I2 * y) / 120.0L);
+    w[3] = (double)((15.0L * I6 * y * y * y - 15.0L * I4 * y * y + 4.0L * I2 * y) / 720.0L);
+    for (int i = 0; i < 4; ++i)
+        if (!(w[i] > 0)) return LBM_EUNSUPPORTED;
+    *cs_out = (double)std::sqrt(y);
+    return LBM_OK;
+}
+
 int compute_constants(const lbm_params *p, lbm_constants *k)
 {
+    if (p->lattice == LBM_D1V7) {
+        double I[5], w[4], cs;
+        int rc = weight_integrals_n(p->stats, 1, p->theta, p->mu, 5, I);
+        if (rc != LBM_OK) return rc;
+        rc = d1v7_constants(I, &cs, w);
+        if (rc != LBM_OK) return rc;
+        *k = lbm_constants{};
+        k->I0 = I[0];
+        k->I2 = I[1];
+        k->I4 = I[2];
+        k->c0 = 1.0 / std::sqrt(I[0]);
+        k->c1 = 1.0 / std::sqrt(I[1]);
+        k->c2 = 1.0 / std::sqrt(I[2]);
+        k->J2 = I[1] * I[1] / (I[2] * I[0]);
+        k->theta_bar = I[1] / I[0];
+        k->cs = cs;
+        for (int s = 0; s < 4; ++s) {
+            k->w[s] = w[s];
+            k->what[s] = w[s] / I[0];
+        }
+        return LBM_OK;
+    }
     int D;
     if (p->lattice == LBM_D2V9)
         D = 2;

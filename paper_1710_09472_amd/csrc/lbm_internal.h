@@ -145,6 +145,41 @@ struct AdjointArgs {
     int accumulate;   // add this step's wave sums to partials instead of overwriting
 };
 
+// Fourth-order thermal model on D1V7 (lbm_thermal.hip), deviations d_a = f_a - rho0 what_a.
+// The equilibrium is what_a p(xi_a) with sum_a what_a p(xi_a) xi_a^k = M_k, k = 0..4; the
+// deviation of p from rho0 has coefficients dc = H^-1 dM, split into the even block
+// (k = 0, 2, 4) and the odd block (k = 1, 3) of the Hankel matrix of the what moments.
+// Constants of the D1V7 thermal step. Inside the step, velocities are the integer e_a
+// (lattice units: u_e = c_s u, thetabar_e = c_s^2 thetabar), so that every power of e_a
+// is exact in FP32; the fields convert to xi = e / c_s only on input and output.
+struct ThermalPhysics {
+    float omega;       // 1 / tau
+    float rho0;
+    float tb_hi, tb_lo;  // T = sum what e^2 = c_s^2 I_2 / I_0 (thetabar_e of the weight), two FP32 parts
+    float g0;          // g held at the weight's value, I_4 I_0 / I_2^2
+    float what[7];     // w / I_0 in the order e = 0, +1, -1, +2, -2, +3, -3
+    float He_inv[9];   // inverse of the even block of e-moments, row-major over (0, 2, 4)
+    float Ho_inv[4];   // inverse of the odd block of e-moments, row-major over (1, 3)
+    double T;          // T in FP64 (init)
+    double cs;         // c_s (conversion of the fields)
+    double what_rho0[7];  // rho0 what_a in FP64 (export)
+};
+
+struct ThermalArgs {
+    int n;             // nodes
+    int stride;        // elements between population arrays
+    ThermalPhysics ph;
+    const float *src;
+    float *dst;
+    const double *rho, *u, *tb;   // init fields (u, tb nullable)
+    float *out_rho, *out_u, *out_tb;  // moment fields (nullable)
+    double *f64;       // export (nullable)
+    double *partials;  // per-block (sum drho, sum j_e, sum dE_e), lattice units (nullable)
+};
+
+// mode 0: step src -> dst; 1: init into dst; 2: fields; 3: export; 4: partial sums
+hipError_t launch_thermal(int mode, const ThermalArgs &a, int nblocks_reduce, hipStream_t st);
+
 // Launchers (lbm_kernels.hip). Each returns hipSuccess or the launch error.
 // force: 0 no field, 1 E only, 2 E and B.
 hipError_t launch_step(int lattice, int storage, int force, const StepArgs &a, hipStream_t st);
@@ -174,6 +209,8 @@ hipError_t launch_seed(int lattice, const Geometry &g, float value_per_unit_e, i
 
 // Host constants (lbm_consts.cpp).
 int weight_integrals(int stats, int D, double theta, double mu, double out[4]);
+int weight_integrals_n(int stats, int D, double theta, double mu, int n, double *out);
+int d1v7_constants(const double I[5], double *cs, double w[4]);
 int compute_constants(const lbm_params *p, lbm_constants *k);
 
 constexpr int kBlock = 256;        // threads per block of the node kernels

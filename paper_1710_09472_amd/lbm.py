@@ -14,7 +14,7 @@ import numpy as np
 PKG = Path(__file__).resolve().parent
 LIB_PATH = PKG / "liblbm_hip.so"
 
-LATTICES = {"D2V9": 0, "D3V19": 1, "D3V15": 2}
+LATTICES = {"D2V9": 0, "D3V19": 1, "D3V15": 2, "D1V7": 3}
 STATS = {"fd": 0, "be": 1, "hermite": 2}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 FORCING = {"source": 0, "shift": 1}
@@ -27,7 +27,7 @@ EXPORTS = [
     "lbm_compute_constants", "lbm_lattice_info", "lbm_buffer_sizes", "lbm_create", "lbm_init",
     "lbm_step", "lbm_step_from", "lbm_moments", "lbm_current", "lbm_get_state", "lbm_set_state",
     "lbm_export_f64", "lbm_set_fields", "lbm_set_tau", "lbm_adjoint_seed", "lbm_adjoint_step",
-    "lbm_density_from_mu", "lbm_mu_from_density",
+    "lbm_density_from_mu", "lbm_mu_from_density", "lbm_init_thermal", "lbm_thetabar", "lbm_energy",
     "lbm_destroy", "lbm_last_error", "lbm_status_string",
 ]
 
@@ -77,6 +77,9 @@ def load_library() -> ctypes.CDLL:
         lib.lbm_buffer_sizes.argtypes = [P, sz, sz, sz, sz]
         lib.lbm_create.argtypes = [P, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
         lib.lbm_init.argtypes = [vp, vp, vp]
+        lib.lbm_init_thermal.argtypes = [vp, vp, vp, vp]
+        lib.lbm_thetabar.argtypes = [vp, vp]
+        lib.lbm_energy.argtypes = [vp, ctypes.POINTER(d)]
         lib.lbm_step.argtypes = [vp, i]
         lib.lbm_step_from.argtypes = [vp, vp, vp]
         lib.lbm_moments.argtypes = [vp, vp, vp]
@@ -257,13 +260,35 @@ class Simulation:
         return t.to(device=self.device, dtype=dtype).contiguous()
 
     # ------------------------------------------------------------------ forward
-    def init(self, rho, u=None):
-        """f = f^eq(rho, u); rho (N,), u (D, N) or None, xi-units."""
+    def init(self, rho, u=None, thetabar=None):
+        """f = f^eq(rho, u); rho (N,), u (D, N) or None, xi-units. The D1V7 thermal model
+        also takes thetabar (N,) (None: the weight's I_2/I_0)."""
         self._rho_in = self._dev(rho, self.torch.float64).reshape(-1)
         self._u_in = None if u is None else self._dev(u, self.torch.float64).reshape(-1)
         if self._rho_in.numel() != self.N or (self._u_in is not None and self._u_in.numel() != self.D * self.N):
             raise ValueError("rho must have N entries and u D*N")
+        if self.lattice == "D1V7":
+            self._tb_in = None if thetabar is None else self._dev(thetabar, self.torch.float64).reshape(-1)
+            if self._tb_in is not None and self._tb_in.numel() != self.N:
+                raise ValueError("thetabar must have N entries")
+            _check(self.lib.lbm_init_thermal(self.h, _ptr(self._rho_in), _ptr(self._u_in), _ptr(self._tb_in)),
+                   self.h)
+            return
+        if thetabar is not None:
+            raise ValueError("thetabar is a field of the D1V7 thermal model")
         _check(self.lib.lbm_init(self.h, _ptr(self._rho_in), _ptr(self._u_in)), self.h)
+
+    def thetabar(self):
+        """thetabar (N,) float32 device tensor of the current state (D1V7 thermal model)."""
+        out = self.torch.empty(self.N, dtype=self.torch.float32, device=self.device)
+        _check(self.lib.lbm_thetabar(self.h, _ptr(out)), self.h)
+        return out
+
+    def energy(self):
+        """sum over nodes of sum_a f_a xi_a^2, FP64 (D1V7 thermal model)."""
+        out = ctypes.c_double()
+        _check(self.lib.lbm_energy(self.h, ctypes.byref(out)), self.h)
+        return out.value
 
     def step(self, n=1):
         _check(self.lib.lbm_step(self.h, int(n)), self.h)

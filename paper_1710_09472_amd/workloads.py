@@ -33,6 +33,12 @@ The paper's own setups (Sec. 9.3, 9.4), with its velocity-shift forcing:
 
 These use density 1 where the paper starts from mu = 1 (rho = I_0): the update is
 homogeneous of degree one in f, so the velocity field does not depend on that scale.
+
+The fourth-order thermal model (D1V7):
+
+* ``thermal_1d``  D1V7, n nodes (default 2^24) periodic, Fermi-Dirac weight theta = 1/4,
+  mu = 1 (moderately degenerate, z = e^4), rho = 1 + 0.01 N(0,1), u = 0.01 N(0,1),
+  thetabar = thetabar_ref (1 + 0.01 N(0,1)) (seed 6, independent draws), tau = 0.8.
 """
 from __future__ import annotations
 
@@ -59,6 +65,9 @@ class Workload:
     notes: dict = field(default_factory=dict)
     forcing: str = "source"           # "source" (xi-dependent term) or "shift" (velocity shift)
     slip: int = 0                     # free-slip wall planes: 1 y, 2 z (bits)
+    thetabar: np.ndarray | None = None  # (N,) float64, D1V7 thermal model (None: the weight's)
+    theta: float = 1.0 / 270.0        # weight parameters (electron model by default)
+    mu: float = 1.0
 
     @property
     def N(self) -> int:
@@ -66,7 +75,7 @@ class Workload:
 
     @property
     def D(self) -> int:
-        return 2 if self.lattice.startswith("D2") else 3
+        return {"D1": 1, "D2": 2}.get(self.lattice[:2], 3)
 
 
 def _grid(nx, ny, nz=1):
@@ -279,6 +288,19 @@ def ohm_paper_3d(Ex: float = 1e-7, seed: int = 5, steps: int = 20000) -> Workloa
 def poiseuille_paper_2d(tau: float = 0.8, n: int = 256, steps: int = 1_000_000) -> Workload:
     return Workload("poiseuille_paper_2d", "D2V9", n, n, 1, tau=tau, steps=steps, E=(1e-8, 0.0, 0.0),
                     rho=np.ones(n * n), mask=channel_mask_2d(n, n), forcing="shift")
+
+
+def thermal_1d(thetabar_ref: float, n: int = 1 << 24, seed: int = 6, tau: float = 0.8,
+               theta: float = 0.25, mu: float = 1.0, amp: float = 0.01) -> Workload:
+    """D1V7 thermal workload: white-noise density, velocity and thetabar perturbations of
+    relative size amp around (1, 0, thetabar_ref); thetabar_ref is the weight's I_2/I_0,
+    given by the caller."""
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + amp * rng.standard_normal(n)
+    u = amp * rng.standard_normal((1, n))
+    tb = thetabar_ref * (1.0 + amp * rng.standard_normal(n))
+    return Workload("thermal_1d", "D1V7", n, 1, 1, tau=tau, steps=0, rho=rho, u=u, thetabar=tb,
+                    theta=theta, mu=mu)
 
 
 def random_fields(lattice: str, nx: int, ny: int, nz: int = 1, seed: int = 0, drho: float = 0.05,

@@ -195,3 +195,43 @@ def test_scheme_validation():
     for p in (lbm.make_params("D2V9", 16, 3, forcing="shift", slip=lbm.SLIP_Y),
               lbm.make_params("D3V19", 8, 3, 3, forcing="shift", slip=lbm.SLIP_Y | lbm.SLIP_Z)):
         assert lib.lbm_buffer_sizes(ctypes.byref(p), ctypes.byref(sizes), None, None, None) == lbm.LBM_OK
+
+
+@pytest.mark.parametrize("stats,theta,mu", [("fd", 1.0 / 270.0, 1.0), ("fd", 0.25, 1.0), ("fd", 1.0, -5.0),
+                                            ("hermite", 1.0, 0.0)])
+def test_d1v7_constants_match_the_oracle(stats, theta, mu):
+    """D1V7 of App. A: the library's c_s (printed closed form, long double) and weights
+    against the oracle's (mpmath)."""
+    from oracle import constants as C
+
+    k = lbm.compute_constants("D1V7", stats, theta, mu)
+    o = C.d1v7(stats, "1/270" if theta == 1.0 / 270.0 else theta, mu)
+    assert abs(k["cs"] - float(o["cs"])) < 1e-12 * float(o["cs"])
+    for s in range(4):
+        assert abs(k["w"][s] - float(o["w"][s])) < 1e-12 * float(o["w"][s]), s
+    Q, D, e = lbm.lattice_info("D1V7")
+    assert (Q, D) == (7, 1) and list(e[:, 0]) == [0, 1, -1, 2, -2, 3, -3] and not e[:, 1:].any()
+
+
+def test_thermal_model_validation_without_device_work():
+    assert _rc(lbm.make_params("D1V7", 64, 2)) == lbm.LBM_EINVAL                 # ny must be 1
+    assert _rc(lbm.make_params("D1V7", 64, E=(1e-6, 0, 0))) == lbm.LBM_EINVAL     # no fields
+    assert _rc(lbm.make_params("D1V7", 64, storage="f16")) == lbm.LBM_EUNSUPPORTED
+    assert _rc(lbm.make_params("D1V7", 64)) == lbm.LBM_OK
+    lib = lbm.load_library()
+    h = ctypes.c_void_p()
+    p = lbm.make_params("D1V7", 64, theta=0.25, mu=1.0)
+    a, b, work = ctypes.c_void_p(4096), ctypes.c_void_p(8192), ctypes.c_void_p(1 << 20)
+    assert lib.lbm_create(ctypes.byref(p), ctypes.c_void_p(64), None, a, b, work, None,
+                          ctypes.byref(h)) == lbm.LBM_EUNSUPPORTED and not h.value   # no solids
+    assert lib.lbm_create(ctypes.byref(p), None, None, a, None, work, None,
+                          ctypes.byref(h)) == lbm.LBM_EUNSUPPORTED and not h.value   # two buffers
+    assert lib.lbm_create(ctypes.byref(p), None, None, a, b, work, None, ctypes.byref(h)) == lbm.LBM_OK
+    rc_adj = lib.lbm_adjoint_seed(h, 0, ctypes.c_double(1.0), ctypes.c_void_p(4096))
+    assert rc_adj == lbm.LBM_EUNSUPPORTED
+    lib.lbm_destroy(h)
+    # the 2D/3D kernels reject thetabar queries
+    p2 = lbm.make_params("D2V9", 8, 8)
+    assert lib.lbm_create(ctypes.byref(p2), None, None, a, b, work, None, ctypes.byref(h)) == lbm.LBM_OK
+    assert lib.lbm_thetabar(h, ctypes.c_void_p(4096)) == lbm.LBM_EUNSUPPORTED
+    lib.lbm_destroy(h)
