@@ -311,18 +311,32 @@ void fill_thermal(lbm_t h)
     const long double det = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
                             E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
                             E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+    long double Ei[3][3];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             // inverse = adjugate / det; adj[i][j] = cofactor of E[j][i]
             const int r0 = (j + 1) % 3, r1 = (j + 2) % 3, c0 = (i + 1) % 3, c1 = (i + 2) % 3;
-            t.He_inv[3 * i + j] = (float)((E[r0][c0] * E[r1][c1] - E[r0][c1] * E[r1][c0]) / det);
+            Ei[i][j] = (E[r0][c0] * E[r1][c1] - E[r0][c1] * E[r1][c0]) / det;
         }
     const long double O[2][2] = {{m[2], m[4]}, {m[4], m[6]}};
     const long double dO = O[0][0] * O[1][1] - O[0][1] * O[1][0];
-    t.Ho_inv[0] = (float)(O[1][1] / dO);
-    t.Ho_inv[1] = (float)(-O[0][1] / dO);
-    t.Ho_inv[2] = (float)(-O[1][0] / dO);
-    t.Ho_inv[3] = (float)(O[0][0] / dO);
+    const long double Oi[2][2] = {{O[1][1] / dO, -O[0][1] / dO}, {-O[1][0] / dO, O[0][0] / dO}};
+    // With D = dE - T drho and dtb = D / rho - u^2, the targets split into linear parts and
+    // remainders of second order:
+    //   dM_3 = 3 T j + r3,   r3 = j (u^2 + 3 dtb)
+    //   dM_4 = 3 g0 (2 T D + T^2 drho) + r4,   r4 = rho [u^2 (u^2 + 6 dtb + 6 T (1 - g0)) + 3 g0 dtb^2]
+    // and H^-1 applied to the weight's own moments (m0, m2, m4) = (1, T, 3 g0 T^2) is (1, 0, 0),
+    // so the drho column of the even solve is exactly (1, 0, 0).
+    const long double T = m[2], g0 = m[4] / (3.0L * m[2] * m[2]);
+    for (int i = 0; i < 3; ++i) {
+        t.pe[i] = (float)(Ei[i][1] + 6.0L * g0 * T * Ei[i][2]);
+        t.he[i] = (float)Ei[i][2];
+    }
+    for (int i = 0; i < 2; ++i) {
+        t.ko[i] = (float)(Oi[i][0] + 3.0L * T * Oi[i][1]);
+        t.ho[i] = (float)Oi[i][1];
+    }
+    t.k6 = (float)(6.0L * T * (1.0L - g0));
 }
 
 ThermalArgs thermal_args(const lbm_t h)

@@ -158,8 +158,11 @@ struct ThermalPhysics {
     float tb_hi, tb_lo;  // T = sum what e^2 = c_s^2 I_2 / I_0 (thetabar_e of the weight), two FP32 parts
     float g0;          // g held at the weight's value, I_4 I_0 / I_2^2
     float what[7];     // w / I_0 in the order e = 0, +1, -1, +2, -2, +3, -3
-    float He_inv[9];   // inverse of the even block of e-moments, row-major over (0, 2, 4)
-    float Ho_inv[4];   // inverse of the odd block of e-moments, row-major over (1, 3)
+    // Polynomial coefficients c = H^-1 M of the moment targets, with the linear parts of
+    // M_3, M_4 folded in (H the Hankel matrices of the e-moments of what, in long double):
+    //   (c0, c2, c4) = (drho, 0, 0) + pe * D + he * r4,   (c1, c3) = ko * j + ho * r3
+    float pe[3], he[3], ko[2], ho[2];
+    float k6;          // 6 T (1 - g0)
     double T;          // T in FP64 (init)
     double cs;         // c_s (conversion of the fields)
     double what_rho0[7];  // rho0 what_a in FP64 (export)

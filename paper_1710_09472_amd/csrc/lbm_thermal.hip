@@ -12,15 +12,13 @@
 //
 // Precision. Deviations are formed throughout, so that rounding is relative to the
 // departure from the weight's state, not to the populations. Velocities are the
-// integer e_a (u and thetabar in lattice units), so every power of e_a is exact; the
-// FP32 constants (what, the Hankel inverses) are not exactly consistent with each other,
-// and a fixed mismatch of the equilibrium's moments would act on every step in the same
-// direction (a drift of the conserved totals, a shift of the sound speed through M_3,
-// the energy flux). One residual step removes it: the moments 1..4 of the polynomial's
-// populations are taken again and their differences from the targets are put back on
-// e = +-1, +-2 (a 2x2 solve per parity, with exact integer matrices); the rest population
-// closes the mass. The equilibrium then carries moments 0..4 up to the rounding of the
-// sums, as the projection does in exact arithmetic.
+// integer e_a (u and thetabar in lattice units), so every power of e_a is exact. The
+// polynomial's coefficients come from the moment deviations with the linear parts of
+// M_3 and M_4 folded into constants computed in long double: only remainders of second
+// order are combined at run time, so no coefficient is a small difference of large terms.
+// Populations e = +-2, +-3 take the polynomial's values; e = +-1 then carry the node's
+// momentum and second moment and e = 0 its mass (a closure on the conserved moments), so
+// that no fixed mismatch of the FP32 constants can drift the conserved totals.
 #include "lbm_device.h"
 
 namespace lbm {
@@ -30,8 +28,6 @@ constexpr int kQ7 = 7;
 __device__ constexpr int kE7[kQ7] = {0, 1, -1, 2, -2, 3, -3};
 __device__ constexpr float kEf[kQ7] = {0.f, 1.f, -1.f, 2.f, -2.f, 3.f, -3.f};
 __device__ constexpr float kE2[kQ7] = {0.f, 1.f, 1.f, 4.f, 4.f, 9.f, 9.f};
-__device__ constexpr float kE3[kQ7] = {0.f, 1.f, -1.f, 8.f, -8.f, 27.f, -27.f};
-__device__ constexpr float kE4[kQ7] = {0.f, 1.f, 1.f, 16.f, 16.f, 81.f, 81.f};
 
 __device__ __forceinline__ unsigned wrap_shift(int x, int e, int n)
 {
@@ -55,43 +51,39 @@ __device__ __forceinline__ ThermalNode thermal_equilibrium(const ThermalPhysics 
     m.rho = p.rho0 + drho;
     const float inv = 1.0f / m.rho;
     m.u = j * inv;
-    // thetabar - T = (dE - T drho) / rho - u^2   (sum rho0 what e^2 = rho0 T)
-    const float dtb = (dE - __builtin_fmaf(p.tb_hi, drho, p.tb_lo * drho)) * inv - m.u * m.u;
-    m.dtb = dtb;
-    const float tb = p.tb_hi + dtb;
     const float u2 = m.u * m.u;
-    const float dM3 = j * (u2 + 3.0f * tb);
-    // rho tb^2 g0 - rho0 T^2 g0 = g0 [drho tb^2 + rho0 dtb (2 T + dtb)]
-    const float dA = p.g0 * __builtin_fmaf(drho, tb * tb, p.rho0 * dtb * (2.0f * p.tb_hi + dtb));
-    const float dM4 = __builtin_fmaf(j * m.u, u2 + 6.0f * tb, 3.0f * dA);
-    const float c0 = p.He_inv[0] * drho + p.He_inv[1] * dE + p.He_inv[2] * dM4;
-    const float c2 = p.He_inv[3] * drho + p.He_inv[4] * dE + p.He_inv[5] * dM4;
-    const float c4 = p.He_inv[6] * drho + p.He_inv[7] * dE + p.He_inv[8] * dM4;
-    const float c1 = p.Ho_inv[0] * j + p.Ho_inv[1] * dM3;
-    const float c3 = p.Ho_inv[2] * j + p.Ho_inv[3] * dM3;
-    float r1 = j, r2 = dE, r3 = dM3, r4 = dM4;
+    // D = dE - T drho = rho (thetabar - T) + rho u^2   (sum rho0 what e^2 = rho0 T)
+    const float D = dE - __builtin_fmaf(p.tb_hi, drho, p.tb_lo * drho);
+    const float dtb = __builtin_fmaf(D, inv, -u2);
+    m.dtb = dtb;
+    // second-order remainders of the targets dM_3, dM_4 (their linear parts are in pe, ko)
+    const float r3 = j * __builtin_fmaf(3.0f, dtb, u2);
+    const float r4 = m.rho * __builtin_fmaf(u2, __builtin_fmaf(6.0f, dtb, u2) + p.k6, 3.0f * p.g0 * dtb * dtb);
+    const float c0 = __builtin_fmaf(p.he[0], r4, __builtin_fmaf(p.pe[0], D, drho));
+    const float c2 = __builtin_fmaf(p.he[1], r4, p.pe[1] * D);
+    const float c4 = __builtin_fmaf(p.he[2], r4, p.pe[2] * D);
+    const float c1 = __builtin_fmaf(p.ho[0], r3, p.ko[0] * j);
+    const float c3 = __builtin_fmaf(p.ho[1], r3, p.ko[1] * j);
 #pragma unroll
-    for (int a = 1; a < kQ7; ++a) {
+    for (int a = 3; a < kQ7; ++a) {
         const float x = kEf[a];
         const float poly = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(__builtin_fmaf(c4, x, c3), x, c2), x, c1), x, c0);
         feq[a] = p.what[a] * poly;
-        r1 = __builtin_fmaf(-feq[a], kEf[a], r1);
-        r2 = __builtin_fmaf(-feq[a], kE2[a], r2);
-        r3 = __builtin_fmaf(-feq[a], kE3[a], r3);
-        r4 = __builtin_fmaf(-feq[a], kE4[a], r4);
     }
-    // odd: o1 + 2 o2 = r1, o1 + 8 o2 = r3; even: s1 + 4 s2 = r2, s1 + 16 s2 = r4, with
-    // o_k, s_k the difference and the sum of the corrections on e = +k and e = -k
-    const float o2 = (r3 - r1) * (1.0f / 6.0f), o1 = __builtin_fmaf(-2.0f, o2, r1);
-    const float s2 = (r4 - r2) * (1.0f / 12.0f), s1 = __builtin_fmaf(-4.0f, s2, r2);
-    feq[1] += 0.5f * (s1 + o1);
-    feq[2] += 0.5f * (s1 - o1);
-    feq[3] += 0.5f * (s2 + o2);
-    feq[4] += 0.5f * (s2 - o2);
+    // conservation closure: e = +-1 carry the node's momentum and second moment, e = 0 its
+    // mass, so that the collision conserves all three up to the rounding of these sums
+    float mj = j, mE = dE;
+#pragma unroll
+    for (int a = 3; a < kQ7; ++a) {
+        mj = __builtin_fmaf(-feq[a], kEf[a], mj);
+        mE = __builtin_fmaf(-feq[a], kE2[a], mE);
+    }
+    feq[1] = 0.5f * (mE + mj);
+    feq[2] = 0.5f * (mE - mj);
     float sum = 0.f;
 #pragma unroll
     for (int a = 1; a < kQ7; ++a) sum += feq[a];
-    feq[0] = drho - sum;  // mass closure: the equilibrium carries exactly the node's mass
+    feq[0] = drho - sum;
     return m;
 }
 
