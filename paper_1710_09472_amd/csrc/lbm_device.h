@@ -74,8 +74,9 @@ struct VecT<ST, 1> {
 
 // Non-temporal loads: each value is read once per step (measured on MI355X: +3 % on the
 // 4096^2 FP32 step, +5 % on the FP32 duct and the 16-bit disk packing). The x-shifted
-// populations of one-node tiles and the edge values of V-wide tiles are loaded through
-// the cache instead (gather_tile): their lines straddle the neighbouring tile's.
+// populations of one-node tiles, the edge values of V-wide tiles and the shifted 16-bit
+// pairs are loaded through the cache instead (gather_tile): their lines straddle the
+// neighbouring tile's.
 template <int ST, int V>
 __device__ __forceinline__ void vload(const typename Codec<ST>::T *p, float inv_scale, float *f)
 {
@@ -313,6 +314,37 @@ __device__ __forceinline__ void gather_tile(const Geometry &g, const typename Co
             for (int i = 0; i < V; ++i) d[i][q] = f[i];
         } else if constexpr (V == 1) {
             d[0][q] = Codec<ST>::dec(*at32(base, L::ex[q] > 0 ? r.xl : r.xr), inv_scale);
+        } else if constexpr (ST != LBM_F32 && V == 2) {
+            // 16-bit pairs: the two pulled values (x0 - 1, x0) or (x0 + 1, x0 + 2) are adjacent,
+            // so one 4-byte load at 2-byte alignment fetches them (gfx9 global loads allow
+            // it); it stays cached, its lines being shared with the neighbouring lanes. Where
+            // the pair wraps around the row, the address is clamped into the row and the
+            // element from the row's other end comes from a wave-uniform load (a wave lies in
+            // one row). Branch-free: a conditional load would make the wave wait for it.
+            // Measured on MI355X: 4096^2 FP16 +9 %, in place +5 %, against an aligned pair
+            // load plus a 2-byte load of the edge element.
+            using T = typename Codec<ST>::T;
+            typedef uint32_t u32a2 __attribute__((aligned(2)));
+            const uint32_t *row32 = reinterpret_cast<const uint32_t *>(base);  // 4-byte aligned: stride, nx even
+            uint16_t e0, e1;
+            if constexpr (L::ex[q] > 0) {  // (x0 - 1, x0); at x0 = 0 the first is x = nx - 1
+                const bool wrap = r.x0 == 0u;
+                const uint32_t w = *reinterpret_cast<const u32a2 *>(at32(base, wrap ? 0u : r.x0 - 1u));
+                const uint32_t last = row32[(unsigned)g.nx / 2u - 1u];  // (nx - 2, nx - 1)
+                e0 = wrap ? (uint16_t)(last >> 16) : (uint16_t)w;
+                e1 = wrap ? (uint16_t)w : (uint16_t)(w >> 16);
+            } else {  // (x0 + 1, x0 + 2); at x0 = nx - 2 the second is x = 0
+                const bool wrap = r.x0 + 2u >= (unsigned)g.nx;
+                const uint32_t w = *reinterpret_cast<const u32a2 *>(at32(base, wrap ? r.x0 : r.x0 + 1u));
+                const uint32_t first = row32[0];  // (0, 1)
+                e0 = wrap ? (uint16_t)(w >> 16) : (uint16_t)w;
+                e1 = wrap ? (uint16_t)first : (uint16_t)(w >> 16);
+            }
+            T t0, t1;
+            __builtin_memcpy(&t0, &e0, 2);
+            __builtin_memcpy(&t1, &e1, 2);
+            d[0][q] = Codec<ST>::dec(t0, inv_scale);
+            d[1][q] = Codec<ST>::dec(t1, inv_scale);
         } else if constexpr (L::ex[q] > 0) {  // from x - 1
             float f[V];
             vload<ST, V>(at32(base, r.x0), inv_scale, f);
