@@ -29,11 +29,13 @@ __device__ constexpr int kE7[kQ7] = {0, 1, -1, 2, -2, 3, -3};
 __device__ constexpr float kEf[kQ7] = {0.f, 1.f, -1.f, 2.f, -2.f, 3.f, -3.f};
 __device__ constexpr float kE2[kQ7] = {0.f, 1.f, 1.f, 4.f, 4.f, 9.f, 9.f};
 
+// (x - e) mod n for 0 <= x < n, |e| <= 3: one correction for n >= 3, up to three on the
+// shortest grids (n = 1, 2)
 __device__ __forceinline__ unsigned wrap_shift(int x, int e, int n)
 {
     int s = x - e;
-    if (s < 0) s += n;
-    if (s >= n) s -= n;
+    while (s < 0) s += n;
+    while (s >= n) s -= n;
     return (unsigned)s;
 }
 

@@ -90,6 +90,20 @@ def test_thermal_parity(regime, n, steps):
     assert abs(cur[1] - Po) < 1e-6 * Mo and cur[2] == 0 and cur[3] == 0
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 6, 7])
+def test_thermal_shortest_grids(n):
+    """Grids shorter than the longest link (e = 3) wrap several times; n = 6 and 7 have no
+    interior node (3 <= x < n - 3) or one."""
+    m = _oracle(n, 0.8, "degenerate")
+    wl = W.thermal_1d(m.thetabar_ref, n=n, seed=40 + n)
+    sim = _sim(wl)
+    sim.step(25)
+    f = m.run(m.init_state(wl.rho, wl.u[0], wl.thetabar), 25)
+    np.testing.assert_allclose(sim.export_f64().cpu().numpy(), f, rtol=0, atol=2e-6 * np.abs(f).max())
+    cur = sim.current()
+    assert abs(cur[0] / m.totals(f)[0] - 1) < 1e-6
+
+
 def _smooth(n, tb_ref, theta, mu):
     """Long-wavelength fields (three modes each): they keep their size over hundreds of
     steps, so the relative errors stay measured against a signal of fixed size."""
