@@ -20,6 +20,9 @@ What is computed (Coelho & Doria, "Lattice Boltzmann method for semiclassical fl
   isotropic tensor of fourth order is 3) and int omega xi^2n = (2n-1)!! I_2n
   (eq. i2n-cont). (This definition replaces the printed fourth-order expansion, which is
   the same projection written out.)
+* The third-order truncation (K = 3, the order that carries the full momentum equation,
+  Sec. 6) is the same projection onto degree <= 3: p matches M_0..M_3; M_4 of f^eq is then
+  whatever the weight's moments make it, so the energy equation is not the paper's.
 * D1V7 (App. A), exact to order 9: f^eq_a = w_a p(xi_a), xi_a = e_a / c_s.
 * thetabar and g of the local Fermi-Dirac distribution 1/(z^-1 exp((xi-u)^2/theta) + 1)
   in one dimension: rho = sqrt(pi theta) g_1/2(z), rho thetabar = (sqrt(pi)/2)
@@ -138,7 +141,10 @@ class ThermalOracle:
     (rho, u, thetabar) per node; populations f[a, n] in the order of D1V7_E."""
 
     def __init__(self, N: int, tau: float, theta=0.25, mu=1.0, g_mode="const", x_range=(-1.5, 2.0),
-                 stats="fd"):
+                 stats="fd", K=4):
+        if K not in (3, 4):
+            raise ValueError("K is 3 or 4")
+        self.K = int(K)
         k = C.d1v7(stats, theta, mu)
         self.N, self.tau = int(N), float(tau)
         self.cs = float(k["cs"])
@@ -148,7 +154,7 @@ class ThermalOracle:
         I = k["I"]
         dfact = {0: 1, 2: 1, 4: 3, 6: 15, 8: 105}  # (2n-1)!!
         mom = {j: (float(I[j]) * dfact[j] if j % 2 == 0 else 0.0) for j in range(9)}
-        self.H = np.array([[mom[i + j] for j in range(5)] for i in range(5)])
+        self.H = np.array([[mom[i + j] for j in range(self.K + 1)] for i in range(self.K + 1)])
         self.rho_ref = float(I[0])
         self.thetabar_ref = float(I[2] / I[0])
         self.s_ref = self.rho_ref ** 2 / self.thetabar_ref
@@ -165,13 +171,14 @@ class ThermalOracle:
         return _table(*self.x_range)(rho ** 2 / thetabar)
 
     def moments_target(self, rho, u, tb, g):
-        return np.stack([rho, rho * u, rho * (tb + u * u), rho * (u ** 3 + 3 * u * tb),
-                         rho * (u ** 4 + 6 * u * u * tb + 3 * tb * tb * g)])
+        M = [rho, rho * u, rho * (tb + u * u), rho * (u ** 3 + 3 * u * tb),
+             rho * (u ** 4 + 6 * u * u * tb + 3 * tb * tb * g)]
+        return np.stack(M[:self.K + 1])
 
     def equilibrium(self, rho, u, tb, g):
-        """f^eq[a, n] = w_a p_n(xi_a), H c_n = M_n."""
+        """f^eq[a, n] = w_a p_n(xi_a), H c_n = M_n (p of degree K)."""
         c = np.linalg.solve(self.H, self.moments_target(rho, u, tb, g))
-        V = np.stack([self.xi ** k for k in range(5)], axis=1)  # [a, k]
+        V = np.stack([self.xi ** k for k in range(self.K + 1)], axis=1)  # [a, k]
         return self.w[:, None] * (V @ c)
 
     def macro(self, f):

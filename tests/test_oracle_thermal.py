@@ -207,12 +207,39 @@ def test_equilibrium_moments_and_reference(oracle):
     np.testing.assert_allclose(ref[:, 0], m.w, rtol=1e-13)
 
 
-def test_equilibrium_is_the_papers_projection():
-    """omega p(xi) = omega sum_N (1/N!) A_N P_N(xi), A_N = int f^FD P_N, for a moving
+def test_third_order_truncation():
+    """K = 3: moments 0..3 of the local state, the fourth one that of the degree-3
+    polynomial (not rho (u^4 + 6 u^2 thetabar + 3 thetabar^2 g) away from the weight's
+    state); the weight's own state is still the weight; the step conserves mass, momentum
+    and second moment."""
+    m = T.ThermalOracle(40, 0.8, K=3)
+    m4 = T.ThermalOracle(40, 0.8, K=4)
+    rng = np.random.default_rng(7)
+    n = 40
+    rho = m.rho_ref * (1 + 0.05 * rng.uniform(-1, 1, n))
+    u = 0.05 * rng.uniform(-1, 1, n)
+    tb = m.thetabar_ref * (1 + 0.05 * rng.uniform(-1, 1, n))
+    g = np.full(n, m.g_ref)
+    feq = m.equilibrium(rho, u, tb, g)
+    M = m4.moments_target(rho, u, tb, g)
+    for kk in range(4):
+        np.testing.assert_allclose((feq * m.xi[:, None] ** kk).sum(0), M[kk], rtol=1e-12, atol=1e-13)
+    assert np.abs((feq * m.xi[:, None] ** 4).sum(0) - M[4]).max() > 1e-6
+    ref = m.equilibrium(np.array([m.rho_ref]), np.zeros(1), np.array([m.thetabar_ref]), np.array([m.g_ref]))
+    np.testing.assert_allclose(ref[:, 0], m.w, rtol=1e-13)
+    f = m.init_state(rho, u, tb)
+    t0, t1 = m.totals(f), m.totals(m.run(f, 10))
+    for a, b in zip(t0, t1):
+        assert abs(a - b) < 1e-12 * max(1.0, abs(a))
+
+
+@pytest.mark.parametrize("K", [3, 4])
+def test_equilibrium_is_the_papers_projection(K):
+    """omega p(xi) = omega sum_(N<=K) (1/N!) A_N P_N(xi), A_N = int f^FD P_N, for a moving
     Fermi-Dirac state (z = e^3.6, theta = 0.3, u = 0.07) under the theta = 1/4, mu = 1
-    weight, with the polynomials of the Sec. 3 coefficient list."""
+    weight, with the polynomials of the Sec. 3 coefficient list (K = 3 and 4)."""
     theta_w, mu_w = 0.25, 1.0
-    m = T.ThermalOracle(4, 0.8, theta=theta_w, mu=mu_w)
+    m = T.ThermalOracle(4, 0.8, theta=theta_w, mu=mu_w, K=K)
     k = C.coefficients4(1, "fd", theta_w, mu_w)
     P = _poly1d(k)
     x, th, u = mp.mpf("3.6"), mp.mpf("0.3"), mp.mpf("0.07")
@@ -224,22 +251,23 @@ def test_equilibrium_is_the_papers_projection():
     c = np.linalg.solve(m.H, m.moments_target(np.array([float(rho)]), np.array([float(u)]),
                                               np.array([float(tb)]), np.array([float(g)])))[:, 0]
     for v in (-1.3, -0.6, 0.0, 0.45, 1.1):
-        paper = mp.fsum(A[N] * P[N](mp.mpf(v)) / math.factorial(N) for N in range(5))
-        mine = sum(c[j] * v ** j for j in range(5))
+        paper = mp.fsum(A[N] * P[N](mp.mpf(v)) / math.factorial(N) for N in range(K + 1))
+        mine = sum(c[j] * v ** j for j in range(K + 1))
         assert abs(float(paper) - mine) < 1e-11 * max(1.0, abs(mine)), (v, float(paper), mine)
 
 
-def test_hermite_weight_gives_the_hermite_expansion():
-    """Hermite weight, Maxwellian state (g = 1): p = rho sum_n (1/n!) a_n He_n(xi) with
+@pytest.mark.parametrize("K", [3, 4])
+def test_hermite_weight_gives_the_hermite_expansion(K):
+    """Hermite weight, Maxwellian state (g = 1): p = rho sum_(n<=K) (1/n!) a_n He_n(xi) with
     a_1 = u, a_2 = u^2 + t, a_3 = u^3 + 3 u t, a_4 = u^4 + 6 u^2 t + 3 t^2, t = thetabar - 1."""
-    m = T.ThermalOracle(4, 0.8, stats="hermite")
+    m = T.ThermalOracle(4, 0.8, stats="hermite", K=K)
     rho, u, tb = 1.3, 0.17, 0.86
     feq = m.equilibrium(np.array([rho]), np.array([u]), np.array([tb]), np.array([1.0]))[:, 0]
     t = tb - 1
     a = [1, u, u * u + t, u ** 3 + 3 * u * t, u ** 4 + 6 * u * u * t + 3 * t * t]
     He = lambda n, v: [1, v, v * v - 1, v ** 3 - 3 * v, v ** 4 - 6 * v * v + 3][n]
     for i, v in enumerate(m.xi):
-        want = m.w[i] * rho * sum(a[n] * He(n, v) / math.factorial(n) for n in range(5))
+        want = m.w[i] * rho * sum(a[n] * He(n, v) / math.factorial(n) for n in range(K + 1))
         assert abs(feq[i] - want) < 1e-13, (i, feq[i], want)
 
 
