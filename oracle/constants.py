@@ -276,10 +276,12 @@ def coefficients4(D: int, stats: str = "fd", theta="1/270", mu=1.0) -> Coefficie
 @functools.lru_cache(maxsize=None)
 def d1v7(stats: str = "fd", theta="1/270", mu=1.0) -> dict:
     """D1V7 of App. A: c_s from the printed closed form (principal branches of the square
-    and cube roots; the real part is kept, the imaginary part is rounding), one of the
-    positive roots of 12 I_2 - 49 I_4 c_s^2 + 70 I_6 c_s^4 - 35 I_8 c_s^6 = 0, and the
-    printed solution of the quadrature equations for w_0..w_3 (weights of |e| = 0..3).
-    The I_2N are those of eq. (i2n-cont2) with D = 1.
+    and cube roots), one of the positive roots of 12 I_2 - 49 I_4 c_s^2 + 70 I_6 c_s^4
+    - 35 I_8 c_s^6 = 0, and the printed solution of the quadrature equations for w_0..w_3
+    (weights of |e| = 0..3). The I_2N are those of eq. (i2n-cont2) with D = 1. Where the
+    closed form is not real (its imaginary part is more than rounding: then the principal
+    branches have picked a complex root of the cubic) or a weight is not positive, there is
+    no D1V7 lattice for this weight: ValueError.
 
     Returns {"cs", "w": {0: w_0, 1: w_1, 2: w_2, 3: w_3}, "I": {2N: I_2N}} (mpf)."""
     I = {2 * n: weight_integral(1, 2 * n, stats, theta, mu) for n in range(5)}
@@ -289,7 +291,9 @@ def d1v7(stats: str = "fd", theta="1/270", mu=1.0) -> dict:
     R = mp.cbrt(B + mp.sqrt(mp.mpc(4 * A ** 3 + B ** 2)))
     c2 = 2 * I6 / (3 * I8) - 49 * mp.cbrt(2) * I4 / R + 140 * mp.cbrt(2) * I6 ** 2 / (3 * I8 * R) \
         + R / (105 * mp.cbrt(2) * I8)
-    cs = mp.re(mp.sqrt(c2))
+    if not (mp.re(c2) > 0) or abs(mp.im(c2)) > mp.mpf(10) ** (-mp.mp.dps // 2) * abs(c2):
+        raise ValueError(f"D1V7: the closed form for c_s^2 is not real ({c2}) for this weight")
+    cs = mp.sqrt(mp.re(c2))
     y = cs ** 2
     w = {
         0: (360 * I[0] - 150 * I6 * y ** 3 + 420 * I4 * y ** 2 - 490 * I2 * y) / 360,
@@ -297,4 +301,6 @@ def d1v7(stats: str = "fd", theta="1/270", mu=1.0) -> dict:
         2: (30 * I4 * y ** 2 - 15 * I6 * y ** 3 - 9 * I2 * y) / 120,
         3: (15 * I6 * y ** 3 - 15 * I4 * y ** 2 + 4 * I2 * y) / 720,
     }
+    if not all(v > 0 for v in w.values()):
+        raise ValueError("D1V7: a quadrature weight is not positive for this weight")
     return {"cs": cs, "w": w, "I": I}

@@ -197,6 +197,12 @@ def test_scheme_validation():
         assert lib.lbm_buffer_sizes(ctypes.byref(p), ctypes.byref(sizes), None, None, None) == lbm.LBM_OK
 
 
+def test_d1v7_rejected_where_the_oracle_has_no_lattice():
+    for theta, mu in ((0.5, 0.5), (0.5, 0.25)):
+        with pytest.raises(lbm.LbmError):
+            lbm.compute_constants("D1V7", "fd", theta, mu)
+
+
 @pytest.mark.parametrize("stats,theta,mu", [("fd", 1.0 / 270.0, 1.0), ("fd", 0.25, 1.0), ("fd", 1.0, -5.0),
                                             ("hermite", 1.0, 0.0)])
 def test_d1v7_constants_match_the_oracle(stats, theta, mu):
@@ -218,6 +224,10 @@ def test_thermal_model_validation_without_device_work():
     assert _rc(lbm.make_params("D1V7", 64, E=(1e-6, 0, 0))) == lbm.LBM_EINVAL     # no fields
     assert _rc(lbm.make_params("D1V7", 64, storage="f16")) == lbm.LBM_EUNSUPPORTED
     assert _rc(lbm.make_params("D1V7", 64)) == lbm.LBM_OK
+    assert _rc(lbm.make_params("D1V7", 64, order=3)) == lbm.LBM_OK
+    assert _rc(lbm.make_params("D1V7", 64, order=4)) == lbm.LBM_OK
+    assert _rc(lbm.make_params("D1V7", 64, order=2)) == lbm.LBM_EINVAL           # K is 3 or 4
+    assert _rc(lbm.make_params("D2V9", 64, 64, order=3)) == lbm.LBM_EINVAL       # second order only
     lib = lbm.load_library()
     h = ctypes.c_void_p()
     p = lbm.make_params("D1V7", 64, theta=0.25, mu=1.0)

@@ -55,6 +55,16 @@ def test_d1v7_quadrature_equations(stats, theta, mu):
     assert abs(y - max(roots)) < mp.mpf(10) ** -20
 
 
+def test_d1v7_without_a_lattice():
+    """theta = mu = 1/2: the cubic for c_s^2 has one real root and the principal branches of
+    the printed closed form pick a complex one; theta = 1/2, mu = 1/4: the closed form is
+    real but w_3 < 0. No D1V7 lattice exists for these weights."""
+    with pytest.raises(ValueError, match="not real"):
+        C.d1v7("fd", 0.5, 0.5)
+    with pytest.raises(ValueError, match="not positive"):
+        C.d1v7("fd", 0.5, 0.25)
+
+
 @pytest.mark.parametrize("stats,theta,mu", SETS[:2])
 def test_d1v7_printed_weights_solve_the_equations(stats, theta, mu):
     k = C.d1v7(stats, theta, mu)
@@ -332,6 +342,21 @@ def _amplification(m, N=16):
         d[i] = h
         J[:, i] = (m.step(f0 + d.reshape(f0.shape)) - m.step(f0 - d.reshape(f0.shape))).ravel() / (2 * h)
     return np.abs(np.linalg.eigvals(J)).max()
+
+
+def test_stability_of_the_third_order_truncation():
+    """K = 3 matches moments 0..3 only, so the fourth moment of the equilibrium (which
+    sets the heat flux) is the weight's, not the state's: the step is linearly unstable for
+    the strongly degenerate weight theta = 1/4, mu = 1 (g0 = 0.68) at tau = 0.6, 0.8, and
+    stable for theta = 1/2, mu = 0 (g0 = 0.90) and near Boltzmann; K = 4 is stable in all
+    of them."""
+    assert _amplification(T.ThermalOracle(16, 0.6, theta=0.25, mu=1.0, K=3)) > 1.02
+    assert _amplification(T.ThermalOracle(16, 0.8, theta=0.25, mu=1.0, K=3)) > 1.005
+    for theta, mu in ((0.5, 0.0), (1.0, -5.0)):
+        for tau in (0.6, 0.8):
+            assert _amplification(T.ThermalOracle(16, tau, theta=theta, mu=mu, K=3)) < 1 + 1e-6
+    for tau in (0.6, 0.8):
+        assert _amplification(T.ThermalOracle(16, tau, theta=0.25, mu=1.0, K=4)) < 1 + 1e-6
 
 
 def test_stability_of_the_g_held_reading():
