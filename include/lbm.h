@@ -94,6 +94,9 @@ typedef struct {
     int dev_scale_log2; /* LBM_F16 only: stored value is d * 2^dev_scale_log2 (0..40) */
     int forcing;        /* LBM_FORCE_SOURCE or LBM_FORCE_SHIFT */
     int slip;           /* free-slip wall planes: 0, or LBM_SLIP_Y | LBM_SLIP_Z (3D only) */
+    int order;          /* D1V7 only: truncation order K of the equilibrium expansion, 3 (the
+                         * momentum equation, Sec. 6) or 4 (also the energy equation); 0 = 4.
+                         * Must be 0 for D2V9/D3V19 (second order, Sec. 9.1). */
 } lbm_params;
 
 /* Constants the library derives from the parameters (host FP64), exposed for

@@ -147,6 +147,10 @@ int validate(const lbm_params *p, lbm_t h, Sizes *sz)
         if (p->slip) return fail(h, LBM_EINVAL, "D1V7 (thermal model): no free-slip walls");
         if (p->storage != LBM_F32)
             return fail(h, LBM_EUNSUPPORTED, "D1V7 (thermal model): FP32 storage only");
+        if (p->order != 0 && p->order != 3 && p->order != 4)
+            return fail(h, LBM_EINVAL, "D1V7 (thermal model): order must be 3 or 4 (0 = 4)");
+    } else if (p->order != 0) {
+        return fail(h, LBM_EINVAL, "order: the D2V9/D3V19 model is of second order (order must be 0)");
     }
     const double N = (double)p->nx * p->ny * p->nz;
     const double stride = std::ceil(N / 256.0) * 256.0 + stride_pad();
@@ -328,9 +332,19 @@ void fill_thermal(lbm_t h)
     // and H^-1 applied to the weight's own moments (m0, m2, m4) = (1, T, 3 g0 T^2) is (1, 0, 0),
     // so the drho column of the even solve is exactly (1, 0, 0).
     const long double T = m[2], g0 = m[4] / (3.0L * m[2] * m[2]);
-    for (int i = 0; i < 3; ++i) {
-        t.pe[i] = (float)(Ei[i][1] + 6.0L * g0 * T * Ei[i][2]);
-        t.he[i] = (float)Ei[i][2];
+    if (h->p.order == 3) {
+        // third-order truncation: degree 3, even block over (0, 2) only; M_4 is not matched
+        // (c4 = 0, no r4 term), and (1, 0) is again the drho column
+        const long double d2 = m[0] * m[4] - m[2] * m[2];
+        t.pe[0] = (float)(-m[2] / d2);
+        t.pe[1] = (float)(m[0] / d2);
+        t.pe[2] = 0.f;
+        t.he[0] = t.he[1] = t.he[2] = 0.f;
+    } else {
+        for (int i = 0; i < 3; ++i) {
+            t.pe[i] = (float)(Ei[i][1] + 6.0L * g0 * T * Ei[i][2]);
+            t.he[i] = (float)Ei[i][2];
+        }
     }
     for (int i = 0; i < 2; ++i) {
         t.ko[i] = (float)(Oi[i][0] + 3.0L * T * Oi[i][1]);

@@ -8,7 +8,8 @@
 //   M_3 = rho (u^3 + 3 u thetabar), M_4 = rho (u^4 + 6 u^2 thetabar + 3 thetabar^2 g0),
 // matches them with what_a p(e_a), p of degree 4 (the weight-orthogonal projection of
 // the expansion of Sec. 3-5, exact on D1V7's order-9 quadrature), relaxes (BGK) and
-// stores at the node.
+// stores at the node. With order 3 (the truncation that carries the momentum equation,
+// Sec. 6) p has degree 3 and matches M_0..M_3; the host sets c4's constants to zero.
 //
 // Precision. Deviations are formed throughout, so that rounding is relative to the
 // departure from the weight's state, not to the populations. Velocities are the

@@ -39,6 +39,7 @@ class LbmParams(ctypes.Structure):
         ("theta", ctypes.c_double), ("mu", ctypes.c_double), ("tau", ctypes.c_double),
         ("E", ctypes.c_double * 3), ("B", ctypes.c_double * 3), ("rho0", ctypes.c_double),
         ("dev_scale_log2", ctypes.c_int), ("forcing", ctypes.c_int), ("slip", ctypes.c_int),
+        ("order", ctypes.c_int),
     ]
 
 
@@ -115,9 +116,10 @@ def _check(rc, handle=None):
 
 def make_params(lattice="D2V9", nx=1, ny=1, nz=1, tau=0.8, E=(0.0, 0.0, 0.0), B=(0.0, 0.0, 0.0),
                 storage="f32", dev_scale_log2=0, rho0=1.0, stats="fd", theta=1.0 / 270.0, mu=1.0,
-                forcing="source", slip=0) -> LbmParams:
+                forcing="source", slip=0, order=0) -> LbmParams:
     """forcing: "source" (xi-dependent source term) or "shift" (velocity shift);
-    slip: free-slip wall planes, SLIP_Y | SLIP_Z."""
+    slip: free-slip wall planes, SLIP_Y | SLIP_Z; order: D1V7 equilibrium truncation,
+    3 or 4 (0 = 4)."""
     p = LbmParams()
     p.lattice = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
     p.stats = STATS[stats] if isinstance(stats, str) else int(stats)
@@ -130,6 +132,7 @@ def make_params(lattice="D2V9", nx=1, ny=1, nz=1, tau=0.8, E=(0.0, 0.0, 0.0), B=
     p.dev_scale_log2 = int(dev_scale_log2)
     p.forcing = FORCING[forcing] if isinstance(forcing, str) else int(forcing)
     p.slip = int(slip)
+    p.order = int(order)
     return p
 
 
@@ -201,14 +204,15 @@ class Simulation:
 
     def __init__(self, lattice="D2V9", nx=1, ny=1, nz=1, tau=0.8, E=(0.0, 0.0, 0.0), B=(0.0, 0.0, 0.0),
                  storage="f32", dev_scale_log2=0, rho0=1.0, stats="fd", theta=1.0 / 270.0, mu=1.0,
-                 mask=None, s=None, device="cuda", forcing="source", slip=0, work=None, inplace=False):
+                 mask=None, s=None, device="cuda", forcing="source", slip=0, work=None, inplace=False,
+                 order=0):
         import torch
 
         self.torch = torch
         self.lib = load_library()
         self.lattice = lattice
         self.params = make_params(lattice, nx, ny, nz, tau, E, B, storage, dev_scale_log2, rho0, stats, theta, mu,
-                                  forcing, slip)
+                                  forcing, slip, order)
         self.sizes = buffer_sizes(self.params)
         self.Q, self.D, self.e = lattice_info(lattice)
         self.N = nx * ny * nz

@@ -8,6 +8,7 @@
   moments would grow with time there: a sound-speed shift moves the waves' phase), on
   ragged sizes (several 256-node tiles and a tail), in the moderately degenerate
   (theta = 1/4, mu = 1) and the near-Boltzmann (theta = 1, mu = -5) regimes.
+* The third-order truncation (order = 3) against the oracle's K = 3 model, same bar.
 * FP64 totals: mass, momentum and the second moment against the oracle, and their
   conservation over 2000 steps (FP32 rounding only).
 * State hand-over: a state taken mid-run and continued on another handle gives the same
@@ -29,7 +30,7 @@ from paper_1710_09472_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
-REGIMES = {"degenerate": (0.25, 1.0), "boltzmann": (1.0, -5.0)}
+REGIMES = {"degenerate": (0.25, 1.0), "mid": (0.5, 0.0), "boltzmann": (1.0, -5.0)}
 
 
 def _oracle(n, tau, regime):
@@ -37,8 +38,8 @@ def _oracle(n, tau, regime):
     return ThermalOracle(n, tau, theta=theta, mu=mu)
 
 
-def _sim(wl, tau=None):
-    sim = lbm.Simulation("D1V7", wl.nx, 1, 1, tau=tau or wl.tau, theta=wl.theta, mu=wl.mu)
+def _sim(wl, tau=None, order=0):
+    sim = lbm.Simulation("D1V7", wl.nx, 1, 1, tau=tau or wl.tau, theta=wl.theta, mu=wl.mu, order=order)
     sim.init(wl.rho, wl.u, wl.thetabar)
     return sim
 
@@ -88,6 +89,29 @@ def test_thermal_parity(regime, n, steps):
     Mo, Po, Eo = m.totals(f)
     assert abs(cur[0] / Mo - 1) < 1e-6 and abs(E / Eo - 1) < 1e-6
     assert abs(cur[1] - Po) < 1e-6 * Mo and cur[2] == 0 and cur[3] == 0
+
+
+@pytest.mark.parametrize("regime,n,steps", [("mid", 1000, 40), ("boltzmann", 777, 60), ("mid", 300, 200)])
+def test_thermal_third_order_parity(regime, n, steps):
+    """The third-order truncation (order = 3) against the oracle's K = 3 model, in the
+    regimes where it is stable (theta = 1/2, mu = 0 and near Boltzmann; at theta = 1/4,
+    mu = 1 it is linearly unstable for tau <= 1, which the oracle tests state)."""
+    theta, mu = REGIMES[regime]
+    m = ThermalOracle(n, 0.8, theta=theta, mu=mu, K=3)
+    wl = W.thermal_1d(m.thetabar_ref, n=n, seed=17 + n, theta=theta, mu=mu)
+    sim = _sim(wl, order=3)
+    sim.step(steps)
+    f = m.run(m.init_state(wl.rho, wl.u[0], wl.thetabar), steps)
+    er, eu, et = _errors(_state_fields(sim, m), m.macro(f), m.thetabar_ref)
+    print(f"K=3 {regime} n={n} steps={steps}: rho {er:.2e} u {eu:.2e} thetabar {et:.2e}")
+    assert er < TOL and eu < TOL and et < TOL, (er, eu, et)
+    Mo, Po, Eo = m.totals(f)
+    cur, E = sim.current(), sim.energy()
+    assert abs(cur[0] / Mo - 1) < 1e-6 and abs(E / Eo - 1) < 1e-6 and abs(cur[1] - Po) < 1e-6 * Mo
+    # K = 3 and K = 4 differ (the fourth moment of the equilibrium)
+    m4 = _oracle(n, 0.8, regime)
+    f4 = m4.run(m4.init_state(wl.rho, wl.u[0], wl.thetabar), steps)
+    assert np.abs(m4.macro(f4)[2] - m.macro(f)[2]).max() > 100 * et * np.abs(m.macro(f)[2] - m.thetabar_ref).max()
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 6, 7])
