@@ -165,6 +165,29 @@ def inplace_extra(wl, storage: str, k: int, steps: int, warmup: int):
             "state_buffers": 1}
 
 
+def thermal_extra(steps: int, warmup: int):
+    """Throughput of the fourth-order thermal step (D1V7, the 2^24-node thermal_1d
+    workload) and its HBM fraction from HIP events on the library's stream."""
+    from paper_1710_09472_amd.lbm import Simulation
+
+    wl = make_workload("thermal_1d")
+    sim = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, theta=wl.theta, mu=wl.mu)
+    sim.init(wl.rho, wl.u, wl.thetabar)
+    w, e = timed_steps(sim, steps, warmup)
+    alg = algorithmic_bytes(wl, sim.Q, 4)
+    sim.close()
+    gbs = alg / (e / steps) / 1e9
+    one = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, theta=wl.theta, mu=wl.mu, inplace=True)
+    one.init(wl.rho, wl.u, wl.thetabar)
+    w1, e1 = timed_steps(one, steps, warmup + (warmup % 2))
+    one.close()
+    return {"workload": "thermal_1d: D1V7 2^24 nodes, K = 4, FP32", "MLUPS": round(wl.N * steps / w / 1e6, 1),
+            "ms_per_step": round(w / steps * 1e3, 5), "achieved_GBs": round(gbs, 1),
+            "hbm_frac": round(gbs / 8000.0, 4),
+            "inplace": {"MLUPS": round(wl.N * steps / w1 / 1e6, 1), "ms_per_step": round(w1 / steps * 1e3, 5),
+                        "achieved_GBs": round(alg / (e1 / steps) / 1e9, 1), "state_buffers": 1}}
+
+
 def adjoint_ratio(wl, steps: int, warmup: int):
     """Average time of one adjoint step (reverse pull, transposed collision and force,
     FP64 per-wave partials of dJ/dE and dJ/dtau held across steps and reduced on the
@@ -367,8 +390,8 @@ def main():
     elem = 4 if st == "f32" else 2
     k16 = F16_SCALE[args.workload] if st == "f16" else 0
     thermal = wl.lattice == "D1V7"
-    if thermal and (st != "f32" or args.inplace):
-        sys.exit("thermal_1d: FP32 storage and two state buffers only")
+    if thermal and st != "f32":
+        sys.exit("thermal_1d: FP32 storage only")
     sim = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E, B=wl.B, storage=st,
                      dev_scale_log2=k16, mask=wl.mask, s=wl.s, forcing=wl.forcing, slip=wl.slip,
                      inplace=args.inplace, theta=wl.theta, mu=wl.mu)
@@ -407,8 +430,10 @@ def main():
                              "checkpointed_128cube": adjoint_pipeline()}
         extras["inplace"] = {"f32": inplace_extra(wl, "f32", 0, args.steps, args.warmup),
                              "f16": inplace_extra(wl, "f16", F16_SCALE["throughput_2d"], args.steps, args.warmup)}
+        extras["thermal"] = thermal_extra(args.steps, args.warmup)
 
-    kernel = ("k_thermal_step" if thermal else
+    kernel = ("k_thermal_aa_pull+k_thermal_aa_local" if thermal and args.inplace else
+              "k_thermal_step" if thermal else
               "k_step_aa_pull+k_step_aa_local" if args.inplace else "k_step") + \
         f"<{wl.lattice},{st.upper()}" + (",mask" if wl.mask is not None else "") + \
         (",slip" if wl.slip else "") + (",soft" if wl.s is not None else "") + \
@@ -441,6 +466,7 @@ def main():
         out["storage16"] = extras.get("f16") and {"f16": extras["f16"], "bf16": extras["bf16"]}
         out["adjoint"] = extras.get("adjoint")
         out["inplace"] = extras.get("inplace")
+        out["thermal"] = extras.get("thermal")
     out["mass_after_run"] = tot[0]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -454,7 +454,6 @@ int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *s
     if (state_a == state_b) return fail(nullptr, LBM_EINVAL, "state_a and state_b must be distinct buffers");
     if (p->lattice == LBM_D1V7) {
         if (mask || s) return fail(nullptr, LBM_EUNSUPPORTED, "D1V7 (thermal model): no solids or porosity");
-        if (!state_b) return fail(nullptr, LBM_EUNSUPPORTED, "D1V7 (thermal model): two state buffers needed");
     }
     lbm_s *h = new (std::nothrow) lbm_s;
     if (!h) return fail(nullptr, LBM_EDEVICE, "out of host memory");
@@ -579,6 +578,16 @@ int lbm_step(lbm_t h, int nsteps)
     a.ph = h->ph;
     a.links = links_of(h);
     a.remap = use_xcd_remap(h->p.lattice, has_solids(h), h->s != nullptr);
+    if (h->thermal && h->aa) {
+        ThermalArgs ta = thermal_args(h);
+        ta.src = ta.dst = static_cast<float *>(h->buf[0]);
+        for (int t = 0; t < nsteps; ++t) {
+            const hipError_t e = launch_thermal(5 + h->parity, ta, 0, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "in-place thermal step kernel launch");
+            h->parity ^= 1;
+        }
+        return LBM_OK;
+    }
     if (h->thermal) {
         ThermalArgs ta = thermal_args(h);
         for (int t = 0; t < nsteps; ++t) {
@@ -638,6 +647,7 @@ static int thermal_gather(lbm_t h, const void *state, float *rho, float *u, floa
 {
     ThermalArgs a = thermal_args(h);
     a.src = static_cast<const float *>(state ? state : h->buf[h->cur]);
+    a.odd = (!state && h->aa && h->parity) ? 1 : 0;
     a.out_rho = rho;
     a.out_u = u;
     a.out_tb = tb;
@@ -761,6 +771,14 @@ int lbm_get_state(lbm_t h, void *dst)
     if (!dst) return fail(h, LBM_EINVAL, "dst is required");
     if (h->aa && h->parity) {
         if (dst == h->buf[0]) return fail(h, LBM_EINVAL, "dst must not be the handle's own state buffer");
+        if (h->thermal) {
+            ThermalArgs ta = thermal_args(h);
+            ta.src = static_cast<const float *>(h->buf[0]);
+            ta.dst = static_cast<float *>(dst);
+            const hipError_t e = launch_thermal(7, ta, 0, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "state layout kernel launch");
+            return LBM_OK;
+        }
         StepArgs a{};
         a.g = h->g;
         a.ph = h->ph;

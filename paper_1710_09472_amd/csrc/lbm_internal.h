@@ -178,9 +178,11 @@ struct ThermalArgs {
     float *out_rho, *out_u, *out_tb;  // moment fields (nullable)
     double *f64;       // export (nullable)
     double *partials;  // per-block (sum drho, sum j_e, sum dE_e), lattice units (nullable)
+    int odd;           // src holds the streamed ("odd") layout of the in-place step
 };
 
-// mode 0: step src -> dst; 1: init into dst; 2: fields; 3: export; 4: partial sums
+// mode 0: step src -> dst; 1: init into dst; 2: fields; 3: export; 4: partial sums;
+// 5, 6: the two phases of the in-place step (src == dst); 7: odd layout src -> even dst
 hipError_t launch_thermal(int mode, const ThermalArgs &a, int nblocks_reduce, hipStream_t st);
 
 // Launchers (lbm_kernels.hip). Each returns hipSuccess or the launch error.

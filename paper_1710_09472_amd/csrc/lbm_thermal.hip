@@ -29,6 +29,7 @@ constexpr int kQ7 = 7;
 __device__ constexpr int kE7[kQ7] = {0, 1, -1, 2, -2, 3, -3};
 __device__ constexpr float kEf[kQ7] = {0.f, 1.f, -1.f, 2.f, -2.f, 3.f, -3.f};
 __device__ constexpr float kE2[kQ7] = {0.f, 1.f, 1.f, 4.f, 4.f, 9.f, 9.f};
+__device__ constexpr int kOpp7[kQ7] = {0, 2, 1, 4, 3, 6, 5};
 
 // (x - e) mod n for 0 <= x < n, |e| <= 3: one correction for n >= 3, up to three on the
 // shortest grids (n = 1, 2)
@@ -50,6 +51,7 @@ struct ThermalNode {
 __device__ __forceinline__ ThermalNode thermal_equilibrium(const ThermalPhysics &p, float drho, float j, float dE,
                                                            float *feq)
 {
+#pragma clang fp contract(off)  // every fused multiply-add is explicit: the same bits in every kernel
     ThermalNode m;
     m.rho = p.rho0 + drho;
     const float inv = 1.0f / m.rho;
@@ -92,6 +94,7 @@ __device__ __forceinline__ ThermalNode thermal_equilibrium(const ThermalPhysics 
 
 __device__ __forceinline__ void thermal_moments(const float *d, float &drho, float &j, float &dE)
 {
+#pragma clang fp contract(off)
     drho = d[0];
     j = 0.f;
     dE = 0.f;
@@ -103,18 +106,32 @@ __device__ __forceinline__ void thermal_moments(const float *d, float &drho, flo
     }
 }
 
+// The pre-collision populations of node x: slot q of x - e_q (the layout the two-buffer
+// step leaves, "even"), or, after the pull phase of the in-place step ("odd"), slot qbar
+// of x itself.
 __device__ __forceinline__ void thermal_pull(const ThermalArgs &a, int x, float *d)
 {
 #pragma unroll
     for (int q = 0; q < kQ7; ++q)
-        d[q] = __builtin_nontemporal_load(at32(a.src + (size_t)q * a.stride, wrap_shift(x, kE7[q], a.n)));
+        d[q] = a.odd ? __builtin_nontemporal_load(at32(a.src + (size_t)kOpp7[q] * a.stride, (unsigned)x))
+                     : __builtin_nontemporal_load(at32(a.src + (size_t)q * a.stride, wrap_shift(x, kE7[q], a.n)));
+}
+
+// post-collision deviations of a node from its pre-collision ones
+__device__ __forceinline__ void thermal_collide(const ThermalPhysics &p, const float *d, float *o)
+{
+    float feq[kQ7], drho, j, dE;
+    thermal_moments(d, drho, j, dE);
+    thermal_equilibrium(p, drho, j, dE, feq);
+#pragma unroll
+    for (int q = 0; q < kQ7; ++q) o[q] = __builtin_fmaf(p.omega, feq[q] - d[q], d[q]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_thermal_step(ThermalArgs a)
 {
     const int x = (int)(blockIdx.x * kBlock + threadIdx.x);
     if (x >= a.n) return;
-    float d[kQ7], feq[kQ7];
+    float d[kQ7], o[kQ7];
     if (x >= 3 && x + 3 < a.n) {
         // no wrap: the rest population is read once (non-temporal); the shifted ones stay
         // cached, since the lines at a tile's edges are shared with the neighbouring tiles
@@ -125,13 +142,56 @@ __global__ __launch_bounds__(kBlock) void k_thermal_step(ThermalArgs a)
     } else {
         thermal_pull(a, x, d);
     }
-    float drho, j, dE;
-    thermal_moments(d, drho, j, dE);
-    thermal_equilibrium(a.ph, drho, j, dE, feq);
+    thermal_collide(a.ph, d, o);
+#pragma unroll
+    for (int q = 0; q < kQ7; ++q) __builtin_nontemporal_store(o[q], at32(a.dst + (size_t)q * a.stride, (unsigned)x));
+}
+
+// In-place step (one buffer, the AA pattern), phase 0: pull as the two-buffer step does
+// (slot q of x - e_q), collide, and store g_q(x) where the opposite population was pulled
+// from, slot qbar of x + e_q; each node writes exactly the locations it read, which no
+// other node touches. The buffer then holds the streamed ("odd") layout: f_q(x) in slot
+// qbar of x.
+__global__ __launch_bounds__(kBlock) void k_thermal_aa_pull(ThermalArgs a)
+{
+    const int x = (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (x >= a.n) return;
+    float *f = a.dst;
+    float d[kQ7], o[kQ7];
+    const bool interior = x >= 3 && x + 3 < a.n;
 #pragma unroll
     for (int q = 0; q < kQ7; ++q)
-        __builtin_nontemporal_store(__builtin_fmaf(a.ph.omega, feq[q] - d[q], d[q]),
-                                    at32(a.dst + (size_t)q * a.stride, (unsigned)x));
+        d[q] = f[(size_t)q * a.stride + (interior ? (unsigned)(x - kE7[q]) : wrap_shift(x, kE7[q], a.n))];
+    thermal_collide(a.ph, d, o);
+#pragma unroll
+    for (int q = 0; q < kQ7; ++q)
+        __builtin_nontemporal_store(o[q], at32(f + (size_t)kOpp7[q] * a.stride,
+                                               interior ? (unsigned)(x + kE7[q]) : wrap_shift(x, -kE7[q], a.n)));
+}
+
+// Phase 1: f_q(x) from slot qbar of x, collide, store g_q(x) in slot q of x (the
+// two-buffer layout again).
+__global__ __launch_bounds__(kBlock) void k_thermal_aa_local(ThermalArgs a)
+{
+    const int x = (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (x >= a.n) return;
+    float *f = a.dst;
+    float d[kQ7], o[kQ7];
+#pragma unroll
+    for (int q = 0; q < kQ7; ++q) d[q] = __builtin_nontemporal_load(at32(f + (size_t)kOpp7[q] * a.stride, (unsigned)x));
+    thermal_collide(a.ph, d, o);
+#pragma unroll
+    for (int q = 0; q < kQ7; ++q) __builtin_nontemporal_store(o[q], at32(f + (size_t)q * a.stride, (unsigned)x));
+}
+
+// Odd layout src -> even layout dst: g_q(y) = src slot qbar of y + e_q.
+__global__ __launch_bounds__(kBlock) void k_thermal_canon(ThermalArgs a)
+{
+    const int y = (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (y >= a.n) return;
+#pragma unroll
+    for (int q = 0; q < kQ7; ++q)
+        a.dst[(size_t)q * a.stride + y] = a.src[(size_t)kOpp7[q] * a.stride + wrap_shift(y, -kE7[q], a.n)];
 }
 
 // Initial state f = f^eq(rho, u, thetabar): the deviations of node x are stored where
@@ -227,6 +287,18 @@ hipError_t launch_thermal(int mode, const ThermalArgs &a, int nblocks_reduce, hi
     case 4:
         if (!a.src || !a.partials || nblocks_reduce < 1) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_thermal_partials, dim3(nblocks_reduce), block, 0, st, a);
+        break;
+    case 5:
+    case 6:
+        if (!a.dst || a.src != a.dst) return hipErrorInvalidValue;
+        if (mode == 5)
+            hipLaunchKernelGGL(k_thermal_aa_pull, grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL(k_thermal_aa_local, grid, block, 0, st, a);
+        break;
+    case 7:
+        if (!a.src || !a.dst || a.src == a.dst) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_thermal_canon, grid, block, 0, st, a);
         break;
     default:
         return hipErrorInvalidValue;

@@ -234,8 +234,8 @@ def test_thermal_model_validation_without_device_work():
     a, b, work = ctypes.c_void_p(4096), ctypes.c_void_p(8192), ctypes.c_void_p(1 << 20)
     assert lib.lbm_create(ctypes.byref(p), ctypes.c_void_p(64), None, a, b, work, None,
                           ctypes.byref(h)) == lbm.LBM_EUNSUPPORTED and not h.value   # no solids
-    assert lib.lbm_create(ctypes.byref(p), None, None, a, None, work, None,
-                          ctypes.byref(h)) == lbm.LBM_EUNSUPPORTED and not h.value   # two buffers
+    assert lib.lbm_create(ctypes.byref(p), None, None, a, None, work, None, ctypes.byref(h)) == lbm.LBM_OK
+    lib.lbm_destroy(h)                                                               # one buffer: in place
     assert lib.lbm_create(ctypes.byref(p), None, None, a, b, work, None, ctypes.byref(h)) == lbm.LBM_OK
     rc_adj = lib.lbm_adjoint_seed(h, 0, ctypes.c_double(1.0), ctypes.c_void_p(4096))
     assert rc_adj == lbm.LBM_EUNSUPPORTED

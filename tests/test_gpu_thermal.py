@@ -13,6 +13,9 @@
   conservation over 2000 steps (FP32 rounding only).
 * State hand-over: a state taken mid-run and continued on another handle gives the same
   bits; lbm_step_from the same as lbm_step.
+* The in-place step (one buffer): against the oracle and bit for bit the two-buffer step,
+  after even and odd step counts, K = 4 and 3; states handed between the two kinds of
+  handle; the shortest grids.
 * Physics: the slow thermal mode decays at the rate of the paper's energy equation
   (eq. energy-cons-eq, heat flux eq. pseudo-heat-flux-eq, g held), linearised, in lattice
   units, to 1 %.
@@ -38,8 +41,9 @@ def _oracle(n, tau, regime):
     return ThermalOracle(n, tau, theta=theta, mu=mu)
 
 
-def _sim(wl, tau=None, order=0):
-    sim = lbm.Simulation("D1V7", wl.nx, 1, 1, tau=tau or wl.tau, theta=wl.theta, mu=wl.mu, order=order)
+def _sim(wl, tau=None, order=0, inplace=False):
+    sim = lbm.Simulation("D1V7", wl.nx, 1, 1, tau=tau or wl.tau, theta=wl.theta, mu=wl.mu, order=order,
+                         inplace=inplace)
     sim.init(wl.rho, wl.u, wl.thetabar)
     return sim
 
@@ -114,6 +118,57 @@ def test_thermal_third_order_parity(regime, n, steps):
     assert np.abs(m4.macro(f4)[2] - m.macro(f)[2]).max() > 100 * et * np.abs(m.macro(f)[2] - m.thetabar_ref).max()
 
 
+@pytest.mark.parametrize("steps", [0, 1, 24, 25])
+@pytest.mark.parametrize("n,order", [(1000, 4), (4099, 4), (777, 3)])
+def test_thermal_inplace(n, order, steps):
+    """The in-place step (one buffer): against the oracle, and bit for bit the two-buffer
+    step (fields, FP64 totals, exported populations, the state lbm_get_state returns, at
+    even and odd step counts)."""
+    regime = "degenerate" if order == 4 else "mid"
+    theta, mu = REGIMES[regime]
+    m = ThermalOracle(n, 0.8, theta=theta, mu=mu, K=order)
+    wl = W.thermal_1d(m.thetabar_ref, n=n, seed=23 + n, theta=theta, mu=mu)
+    one, two = _sim(wl, order=order, inplace=True), _sim(wl, order=order)
+    one.step(steps)
+    two.step(steps)
+    f = m.run(m.init_state(wl.rho, wl.u[0], wl.thetabar), steps)
+    er, eu, et = _errors(_state_fields(one, m), m.macro(f), m.thetabar_ref)
+    assert er < TOL and eu < TOL and et < TOL, (er, eu, et)
+    assert torch.equal(one.export_f64(), two.export_f64())
+    for a, b in zip(_fields(one), _fields(two)):
+        assert np.array_equal(a, b)
+    assert np.array_equal(one.current(), two.current()) and one.energy() == two.energy()
+    st1, st2 = one.get_state(), two.get_state()
+    assert torch.equal(st1, st2)
+    assert torch.equal(two.export_f64(st1), two.export_f64())
+
+
+def test_thermal_inplace_hand_over():
+    """States move between one-buffer and two-buffer handles (lbm_get_state at odd parity
+    gives the two-buffer layout); lbm_step_from of an in-place handle is the two-buffer step."""
+    m = _oracle(4, 0.8, "degenerate")
+    wl = W.thermal_1d(m.thetabar_ref, n=3001, seed=9)
+    ref = _sim(wl)
+    ref.step(30)
+    one = _sim(wl, inplace=True)
+    one.step(13)
+    two = _sim(wl)
+    two.set_state(one.get_state())
+    two.step(17)
+    assert torch.equal(two.export_f64(), ref.export_f64())
+    back = _sim(wl, inplace=True)
+    two2 = _sim(wl)
+    two2.step(11)
+    back.set_state(two2.get_state())
+    back.step(19)
+    assert torch.equal(back.export_f64(), ref.export_f64())
+    dst = one.new_state()
+    src = one.get_state()
+    one.step_from(src, dst)
+    one.step(1)
+    assert torch.equal(one.export_f64(dst), one.export_f64())
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 6, 7])
 def test_thermal_shortest_grids(n):
     """Grids shorter than the longest link (e = 3) wrap several times; n = 6 and 7 have no
@@ -126,6 +181,9 @@ def test_thermal_shortest_grids(n):
     np.testing.assert_allclose(sim.export_f64().cpu().numpy(), f, rtol=0, atol=2e-6 * np.abs(f).max())
     cur = sim.current()
     assert abs(cur[0] / m.totals(f)[0] - 1) < 1e-6
+    one = _sim(wl, inplace=True)  # the in-place step's stores wrap as well
+    one.step(25)
+    assert torch.equal(one.export_f64(), sim.export_f64())
 
 
 def _smooth(n, tb_ref, theta, mu):
