@@ -1,0 +1,78 @@
+"""Hall duct (GPU, through the C ABI): the cross-section profiles of the current,
+<j_x>_x(y, z), <j_y>_x(y, z), <j_z>_x(y, z), j = rho u (xi-units), of the D3V19 duct with
+solid planes y, z in {0, ny - 1}, E = (1e-6, 0, 0), B = (0, 0, 1e-3), tau = 0.7, after its
+5000 steps (omega_c t = 5 rad, a transient: no closed form).
+
+* A duct of the same physics with a 32 x 32 fluid cross-section, 5000 steps, against the
+  FP64 oracle: the profiles to 1e-5 of max|<j_x>|.
+* The 256 x 128 x 128 duct, 5000 steps: the state stays uniform along x bit for bit
+  (uniform start, periodic x, the same arithmetic at every x), so the FP64 oracle on a
+  duct 2 nodes long with the same cross-section follows exactly the same dynamics: the
+  full-size profiles against it to 1e-5 of max|<j_x>|, at all 5000 steps; the profiles are
+  mirror symmetric about the mid-plane in z (j_x, j_y even, j_z odd: the geometry, the
+  lattice and the force E + u x B with B along z are), to FP32 rounding; mass is conserved.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.oracle import OracleModel
+from paper_1710_09472_amd import lbm
+from paper_1710_09472_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+E, B, TAU, STEPS = (1e-6, 0.0, 0.0), (0.0, 0.0, 1e-3), 0.7, 5000
+
+
+def _gpu_profiles(nx, ny, nz):
+    wl = W.hall_duct_3d(nx, ny, nz)
+    sim = lbm.Simulation("D3V19", nx, ny, nz, tau=TAU, E=E, B=B, mask=wl.mask)
+    sim.init(wl.rho)
+    m0 = sim.current()[0]
+    sim.step(STEPS)
+    rho, u = sim.moments()
+    torch.cuda.synchronize()
+    j = (rho.double()[None, :] * u.double().reshape(3, -1)).cpu().numpy().reshape(3, nz, ny, nx)
+    m1 = sim.current()[0]
+    sim.close()
+    return j, m0, m1, wl
+
+
+def test_hall_profiles_against_the_oracle():
+    nx, ny, nz = 8, 34, 34
+    j, m0, m1, wl = _gpu_profiles(nx, ny, nz)
+    m = OracleModel("D3V19", nx, ny, nz, tau=TAU, E=E, B=B)
+    f = m.run(m.init_state(wl.rho, None, wl.mask), STEPS, wl.mask)
+    rho_o, u_o = m.moments(f, wl.mask)
+    jo = (rho_o[None, :] * u_o.reshape(3, -1)).reshape(3, nz, ny, nx)
+    pg, po = j.mean(axis=3), jo.mean(axis=3)
+    scale = np.abs(po[0]).max()
+    err = np.abs(pg - po).max(axis=(1, 2)) / scale
+    print(f"32x32 duct, {STEPS} steps: max <j_x> {scale:.4e}, profile errors (x, y, z) {err}")
+    assert (err < 1e-5).all(), err
+    assert abs(m1 / m0 - 1) < 1e-6
+
+
+def test_hall_profiles_full_duct():
+    nx, ny, nz = 256, 128, 128
+    j, m0, m1, _ = _gpu_profiles(nx, ny, nz)
+    assert (j == j[..., :1]).all()  # uniform along x, bit for bit
+    p = j[..., 0]  # (3, z, y)
+    jx, jy, jz = p
+    scale = np.abs(jx).max()
+    mirror = np.array([np.abs(jx - jx[::-1, :]).max(), np.abs(jy - jy[::-1, :]).max(),
+                       np.abs(jz + jz[::-1, :]).max()]) / scale
+    c = (nz // 2, ny // 2)
+    wl2 = W.hall_duct_3d(2, ny, nz)
+    m = OracleModel("D3V19", 2, ny, nz, tau=TAU, E=E, B=B)
+    f = m.run(m.init_state(wl2.rho, None, wl2.mask), STEPS, wl2.mask)
+    rho_o, u_o = m.moments(f, wl2.mask)
+    po = (rho_o[None, :] * u_o.reshape(3, -1)).reshape(3, nz, ny, 2)[..., 0]
+    err = np.abs(p - po).max(axis=(1, 2)) / np.abs(po[0]).max()
+    print(f"256x128x128 duct, {STEPS} steps: <j_x> centre {jx[c]:.5e} max {scale:.5e}; <j_y> centre {jy[c]:.5e} "
+          f"min {jy.min():.5e} max {jy.max():.5e}; max|<j_z>| {np.abs(jz).max():.3e}; z-mirror defects {mirror}; "
+          f"mass {m0:.10e} -> {m1:.10e}; profile errors against the oracle (x, y, z) {err}")
+    assert (err < 1e-5).all(), err
+    assert (mirror < 1e-5).all(), mirror
+    assert abs(m1 / m0 - 1) < 1e-6
