@@ -207,6 +207,15 @@ int lbm_energy(lbm_t h, double *out);
  * memory. Synchronises the stream. LBM_ENONFINITE if any total is NaN/Inf. */
 int lbm_current(lbm_t h, double out[4]);
 
+/* Convergence measure of the Ohm's-law runs (Sec. 9.4, stopped when it falls below 1e-7):
+ * the average, over the nodes whose speed |u_new| is non-zero (fluid nodes; solids have
+ * u = 0), of | |u_new| - |u_old| | / |u_new|. u (device float[D*N], the layout lbm_moments
+ * writes) holds the new velocity field; speed (device float[N], caller-owned) holds |u_old|
+ * on entry when have_previous != 0 and |u_new| on return (any content when have_previous
+ * is 0, and then *out = 0). Per-node terms in FP64, summed in FP64; *out is host memory.
+ * Synchronises the stream; LBM_ENONFINITE if the average is NaN/Inf. */
+int lbm_speed_change(lbm_t h, const float *u, float *speed, int have_previous, double *out);
+
 /* Copy the current state to / from a caller device buffer of state_bytes (the
  * library's opaque two-buffer layout: post-collision populations of the previous step).
  * With one state buffer after an odd number of steps, lbm_get_state rearranges the

@@ -724,6 +724,25 @@ int lbm_energy(lbm_t h, double *out)
     return LBM_OK;
 }
 
+int lbm_speed_change(lbm_t h, const float *u, float *speed, int have_previous, double *out)
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    if (!u || !speed || !out) return fail(h, LBM_EINVAL, "u, speed and out are required");
+    hipError_t e = launch_speed_change(u, h->D, (int)h->N, speed, have_previous ? 1 : 0, work_parts(h), kReduceBlocks,
+                                       h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "speed change kernel launch");
+    e = launch_reduce_final(work_parts(h), kReduceBlocks, 2, work_out(h), 0, h->stream, work_stage(h));
+    if (e != hipSuccess) return hip_fail(h, e, "reduce kernel launch");
+    double tot[2];
+    e = hipMemcpyAsync(tot, work_out(h), sizeof(tot), hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "copy of totals");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "stream synchronize");
+    *out = (have_previous && tot[1] > 0) ? tot[0] / tot[1] : 0.0;
+    if (!std::isfinite(*out)) return fail(h, LBM_ENONFINITE, "non-finite speed change");
+    return LBM_OK;
+}
+
 int lbm_export_f64(lbm_t h, const void *state, double *dst)
 {
     if (!h) return fail(nullptr, LBM_EINVAL, "null handle");

@@ -199,6 +199,9 @@ hipError_t launch_gather(int lattice, int storage, const GatherArgs &a, int nblo
                          hipStream_t st);
 // Sum per-block partials [nparts][ncomp] (ncomp <= 8) into out (+= if accumulate).
 // `stage` (kReduceStage * ncomp doubles, nullable) enables a two-stage reduction.
+// Convergence measure of Sec. 9.4 (lbm_speed_change): per-block partials [block][2]
+hipError_t launch_speed_change(const float *u, int D, int N, float *speed, int have_prev, double *partials,
+                               int nblocks, hipStream_t st);
 hipError_t launch_reduce_final(const double *partials, int nparts, int ncomp, double *out,
                                int accumulate, hipStream_t st, double *stage);
 int step_vector_width(int lattice, int storage, int nx);

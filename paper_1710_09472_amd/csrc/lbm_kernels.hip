@@ -224,6 +224,41 @@ __device__ __forceinline__ void block_sum_store(double *v, double *out)
     }
 }
 
+// The convergence measure of the Ohm's-law runs (Sec. 9.4): over the nodes whose new
+// speed |u| is non-zero, the sum of | |u_new| - |u_old| | / |u_new| and their count, as
+// FP64 per-block partials [block][2] (grid-stride, wave64 shuffles, LDS across waves);
+// speed[n] <- |u_new| at every node. u is the (D, N) field of lbm_moments (zero at solids).
+__global__ __launch_bounds__(kBlock) void k_speed_change(const float *__restrict__ u, int D, int N,
+                                                         float *__restrict__ speed, int have_prev,
+                                                         double *__restrict__ partials)
+{
+    double acc[2] = {0.0, 0.0};
+    for (int n = (int)(blockIdx.x * kBlock + threadIdx.x); n < N; n += (int)(gridDim.x * kBlock)) {
+        float s2 = 0.f;
+        for (int d = 0; d < D; ++d) {
+            const float v = u[(size_t)d * N + n];
+            s2 = __builtin_fmaf(v, v, s2);
+        }
+        const float s = sqrtf(s2);
+        if (have_prev && s > 0.f) {
+            acc[0] += fabs((double)s - (double)speed[n]) / (double)s;
+            acc[1] += 1.0;
+        }
+        speed[n] = s;
+    }
+    __shared__ double sh[kBlock / 64][2];
+    for (int c = 0; c < 2; ++c)
+        for (int off = 32; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
+    if ((threadIdx.x & 63) == 0)
+        for (int c = 0; c < 2; ++c) sh[threadIdx.x >> 6][c] = acc[c];
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += sh[w][threadIdx.x];
+        partials[(size_t)blockIdx.x * 2 + threadIdx.x] = t;
+    }
+}
+
 // First stage of a two-stage reduction of per-block partials laid out [part][ncomp]:
 // block b sums a contiguous chunk of parts into out[b*ncomp + c] (coalesced reads).
 __global__ __launch_bounds__(kBlock) void k_reduce_stage1(const double *__restrict__ partials, int nparts,
@@ -690,6 +725,14 @@ hipError_t launch_reduce_final(const double *partials, int nparts, int ncomp, do
         nparts = kReduceStage;
     }
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials, nparts, ncomp, out, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_speed_change(const float *u, int D, int N, float *speed, int have_prev, double *partials,
+                               int nblocks, hipStream_t st)
+{
+    if (!u || !speed || !partials || D < 1 || D > 3 || N < 1 || nblocks < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_speed_change, dim3(nblocks), dim3(kBlock), 0, st, u, D, N, speed, have_prev, partials);
     return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ EXPORTS = [
     "lbm_step", "lbm_step_from", "lbm_moments", "lbm_current", "lbm_get_state", "lbm_set_state",
     "lbm_export_f64", "lbm_set_fields", "lbm_set_tau", "lbm_adjoint_seed", "lbm_adjoint_step",
     "lbm_density_from_mu", "lbm_mu_from_density", "lbm_init_thermal", "lbm_thetabar", "lbm_energy",
-    "lbm_destroy", "lbm_last_error", "lbm_status_string",
+    "lbm_speed_change", "lbm_destroy", "lbm_last_error", "lbm_status_string",
 ]
 
 
@@ -81,6 +81,7 @@ def load_library() -> ctypes.CDLL:
         lib.lbm_init_thermal.argtypes = [vp, vp, vp, vp]
         lib.lbm_thetabar.argtypes = [vp, vp]
         lib.lbm_energy.argtypes = [vp, ctypes.POINTER(d)]
+        lib.lbm_speed_change.argtypes = [vp, vp, vp, i, ctypes.POINTER(d)]
         lib.lbm_step.argtypes = [vp, i]
         lib.lbm_step_from.argtypes = [vp, vp, vp]
         lib.lbm_moments.argtypes = [vp, vp, vp]
@@ -312,6 +313,39 @@ class Simulation:
         out = (ctypes.c_double * 4)()
         _check(self.lib.lbm_current(self.h, out), self.h)
         return np.array(out[:])
+
+    def speed_change(self, u, speed, have_previous=True):
+        """Convergence measure of Sec. 9.4 (lbm_speed_change): the average over nodes with
+        non-zero |u| of | |u| - speed | / |u|; speed (float32 (N,) device tensor) is then
+        overwritten with |u|. u as returned by moments()."""
+        out = ctypes.c_double()
+        _check(self.lib.lbm_speed_change(self.h, _ptr(u), _ptr(speed), int(bool(have_previous)), ctypes.byref(out)),
+               self.h)
+        return out.value
+
+    def run_until_steady(self, tol=1e-7, check_every=1000, max_steps=10 ** 6):
+        """Step until the relative speed change of one step (Sec. 9.4: the average over
+        fluid nodes of | |u_new| - |u_old| | / |u_new|) falls below tol, measured between
+        steps k - 1 and k of every check_every steps. Returns (steps taken, last change);
+        the rule was met if the change is below tol (else max_steps passed first). With
+        FP32 storage the measure has a rounding floor of a few 1e-7 once the flow is
+        steady (the speed of every node jitters by about an ulp from step to step), so a
+        tol at or below it may never be met."""
+        if check_every < 1:
+            raise ValueError("check_every must be >= 1")
+        speed = self.torch.empty(self.N, dtype=self.torch.float32, device=self.device)
+        steps, change = 0, float("inf")
+        while steps < max_steps:
+            self.step(check_every - 1)
+            _, u = self.moments()
+            self.speed_change(u, speed, have_previous=False)
+            self.step(1)
+            _, u = self.moments()
+            change = self.speed_change(u, speed)
+            steps += check_every
+            if change < tol:
+                break
+        return steps, change
 
     def export_f64(self, state=None):
         """Pre-collision populations (Q, N) float64 in library order."""
