@@ -33,17 +33,18 @@ from paper_1710_09472_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
-REGIMES = {"degenerate": (0.25, 1.0), "mid": (0.5, 0.0), "boltzmann": (1.0, -5.0)}
+REGIMES = {"degenerate": (0.25, 1.0), "mid": (0.5, 0.0), "boltzmann": (1.0, -5.0), "bose": (1.0, -0.5)}
+STATS = {"bose": "be"}  # the Bose-Einstein weight; the others are Fermi-Dirac
 
 
-def _oracle(n, tau, regime):
+def _oracle(n, tau, regime, K=4):
     theta, mu = REGIMES[regime]
-    return ThermalOracle(n, tau, theta=theta, mu=mu)
+    return ThermalOracle(n, tau, theta=theta, mu=mu, stats=STATS.get(regime, "fd"), K=K)
 
 
-def _sim(wl, tau=None, order=0, inplace=False):
+def _sim(wl, tau=None, order=0, inplace=False, stats="fd"):
     sim = lbm.Simulation("D1V7", wl.nx, 1, 1, tau=tau or wl.tau, theta=wl.theta, mu=wl.mu, order=order,
-                         inplace=inplace)
+                         inplace=inplace, stats=stats)
     sim.init(wl.rho, wl.u, wl.thetabar)
     return sim
 
@@ -116,6 +117,24 @@ def test_thermal_third_order_parity(regime, n, steps):
     m4 = _oracle(n, 0.8, regime)
     f4 = m4.run(m4.init_state(wl.rho, wl.u[0], wl.thetabar), steps)
     assert np.abs(m4.macro(f4)[2] - m.macro(f)[2]).max() > 100 * et * np.abs(m.macro(f)[2] - m.thetabar_ref).max()
+
+
+@pytest.mark.parametrize("n,steps,K", [(1000, 40, 4), (300, 200, 4), (777, 60, 3)])
+def test_thermal_bose_einstein_weight(n, steps, K):
+    """The Bose-Einstein weight (theta = 1, mu = -1/2, g0 = 1.21): parity against the oracle
+    with the same weight, K = 4 and 3, and FP64 totals."""
+    m = _oracle(n, 0.8, "bose", K=K)
+    theta, mu = REGIMES["bose"]
+    wl = W.thermal_1d(m.thetabar_ref, n=n, seed=31 + n, theta=theta, mu=mu)
+    sim = _sim(wl, order=K, stats="be")
+    sim.step(steps)
+    f = m.run(m.init_state(wl.rho, wl.u[0], wl.thetabar), steps)
+    er, eu, et = _errors(_state_fields(sim, m), m.macro(f), m.thetabar_ref)
+    print(f"Bose-Einstein K={K} n={n} steps={steps}: rho {er:.2e} u {eu:.2e} thetabar {et:.2e}")
+    assert er < TOL and eu < TOL and et < TOL, (er, eu, et)
+    Mo, Po, Eo = m.totals(f)
+    cur, E = sim.current(), sim.energy()
+    assert abs(cur[0] / Mo - 1) < 1e-6 and abs(E / Eo - 1) < 1e-6 and abs(cur[1] - Po) < 1e-6 * Mo
 
 
 @pytest.mark.parametrize("steps", [0, 1, 24, 25])
@@ -252,11 +271,13 @@ def _linear_modes(rho, th, g0, tau, k):
     return np.linalg.eig(A)
 
 
-@pytest.mark.parametrize("regime", ["degenerate", "boltzmann"])
+@pytest.mark.parametrize("regime", ["degenerate", "boltzmann", "bose"])
 def test_thermal_mode_decays_as_the_energy_equation(regime):
+    """(For bosons g0 > 1, so the (g - 1) term of the heat flux changes sign.)"""
     theta, mu = REGIMES[regime]
     N, tau = 128, 1.0
-    k = lbm.compute_constants("D1V7", "fd", theta, mu)
+    stats = STATS.get(regime, "fd")
+    k = lbm.compute_constants("D1V7", stats, theta, mu)
     cs, tb_ref = k["cs"], k["I2"] / k["I0"]
     g0 = k["I4"] * k["I0"] / k["I2"] ** 2
     kw = 2 * np.pi / N
@@ -267,7 +288,7 @@ def test_thermal_mode_decays_as_the_energy_equation(regime):
     tb = tb_ref * (1 + 1e-4 * np.sin(kw * x))
     wl = W.Workload("mode", "D1V7", N, 1, 1, tau=tau, steps=0, rho=tb_ref / tb, u=np.zeros((1, N)),
                     thetabar=tb, theta=theta, mu=mu)
-    sim = _sim(wl)
+    sim = _sim(wl, stats=stats)
     ts, amp = [], []
     for t in range(0, 1601, 10):
         if t >= 200:

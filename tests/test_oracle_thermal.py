@@ -31,7 +31,7 @@ import pytest
 from oracle import constants as C
 from oracle import thermal as T
 
-SETS = [("fd", "1/270", 1.0), ("fd", 0.25, 1.0), ("fd", 1.0, -5.0)]
+SETS = [("fd", "1/270", 1.0), ("fd", 0.25, 1.0), ("fd", 1.0, -5.0), ("be", 1.0, -0.5)]
 
 
 @pytest.mark.parametrize("stats,theta,mu", SETS)
