@@ -388,10 +388,10 @@ def main():
     N = wl.N
     st = args.storage
     elem = 4 if st == "f32" else 2
-    k16 = F16_SCALE[args.workload] if st == "f16" else 0
     thermal = wl.lattice == "D1V7"
     if thermal and st != "f32":
         sys.exit("thermal_1d: FP32 storage only")
+    k16 = F16_SCALE[args.workload] if st == "f16" else 0
     sim = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E, B=wl.B, storage=st,
                      dev_scale_log2=k16, mask=wl.mask, s=wl.s, forcing=wl.forcing, slip=wl.slip,
                      inplace=args.inplace, theta=wl.theta, mu=wl.mu)
