@@ -41,7 +41,7 @@ PROFILE_DIR = ROOT / "profiles"
 
 # dev_scale_log2 of the FP16 runs: max|deviation| x 2^k near 2^12 for each workload
 F16_SCALE = {"throughput_2d": 12, "hall_duct_3d": 28, "porous_ohm_2d": 25, "soft_porous_3d": 28,
-             "ohm_paper_2d": 30, "ohm_paper_3d": 30, "poiseuille_paper_2d": 30}
+             "ohm_paper_2d": 30, "ohm_paper_3d": 30, "poiseuille_paper_2d": 30, "thermal_1d": 17}
 
 
 WORKLOAD_DESC = {
@@ -389,8 +389,6 @@ def main():
     st = args.storage
     elem = 4 if st == "f32" else 2
     thermal = wl.lattice == "D1V7"
-    if thermal and st != "f32":
-        sys.exit("thermal_1d: FP32 storage only")
     k16 = F16_SCALE[args.workload] if st == "f16" else 0
     sim = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E, B=wl.B, storage=st,
                      dev_scale_log2=k16, mask=wl.mask, s=wl.s, forcing=wl.forcing, slip=wl.slip,

@@ -40,7 +40,7 @@ typedef struct lbm_s *lbm_t;
  * under the electron weight its rest weight is negative, which Sec. 8 forbids.
  * LBM_D1V7 (App. A, e = 0, +-1, +-2, +-3, quadrature of order 9) carries the
  * fourth-order thermal model: the equilibrium expanded to K = 4 (Sec. 3-6; K = 3 with
- * lbm_params.order = 3), periodic in x (ny = nz = 1), FP32 storage, no fields, solids or
+ * lbm_params.order = 3), periodic in x (ny = nz = 1), FP32 or 16-bit storage, no fields, solids or
  * porosity, two state buffers or one (the in-place step, as for the other lattices);
  * see lbm_init_thermal. */
 enum { LBM_D2V9 = 0, LBM_D3V19 = 1, LBM_D3V15 = 2, LBM_D1V7 = 3 };

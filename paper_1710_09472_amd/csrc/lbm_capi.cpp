@@ -145,8 +145,6 @@ int validate(const lbm_params *p, lbm_t h, Sizes *sz)
         for (int i = 0; i < 3; ++i)
             if (p->E[i] != 0.0 || p->B[i] != 0.0) return fail(h, LBM_EINVAL, "D1V7 (thermal model): no E or B");
         if (p->slip) return fail(h, LBM_EINVAL, "D1V7 (thermal model): no free-slip walls");
-        if (p->storage != LBM_F32)
-            return fail(h, LBM_EUNSUPPORTED, "D1V7 (thermal model): FP32 storage only");
         if (p->order != 0 && p->order != 3 && p->order != 4)
             return fail(h, LBM_EINVAL, "D1V7 (thermal model): order must be 3 or 4 (0 = 4)");
     } else if (p->order != 0) {
@@ -294,6 +292,8 @@ void fill_thermal(lbm_t h)
     const lbm_constants &k = h->k;
     t.omega = (float)(1.0 / h->p.tau);
     t.rho0 = (float)h->p.rho0;
+    t.scale = h->p.storage == LBM_F16 ? (float)std::ldexp(1.0, h->p.dev_scale_log2) : 1.f;
+    t.inv_scale = 1.f / t.scale;  // a power of two: exact
     long double what[7], m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // e-moments sum what e^j
     for (int a = 0; a < 7; ++a) {
         what[a] = (long double)k.w[std::abs(kD1V7E[a])] / (long double)k.I0;
@@ -541,8 +541,8 @@ int lbm_init_thermal(lbm_t h, const double *rho, const double *u, const double *
     a.rho = rho;
     a.u = u;
     a.tb = thetabar;
-    a.dst = static_cast<float *>(h->buf[h->cur]);
-    const hipError_t e = launch_thermal(1, a, 0, h->stream);
+    a.dst = h->buf[h->cur];
+    const hipError_t e = launch_thermal(1, h->p.storage, a, 0, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "thermal init kernel launch");
     h->initialized = true;
     h->parity = 0;
@@ -580,9 +580,9 @@ int lbm_step(lbm_t h, int nsteps)
     a.remap = use_xcd_remap(h->p.lattice, has_solids(h), h->s != nullptr);
     if (h->thermal && h->aa) {
         ThermalArgs ta = thermal_args(h);
-        ta.src = ta.dst = static_cast<float *>(h->buf[0]);
+        ta.src = ta.dst = h->buf[0];
         for (int t = 0; t < nsteps; ++t) {
-            const hipError_t e = launch_thermal(5 + h->parity, ta, 0, h->stream);
+            const hipError_t e = launch_thermal(5 + h->parity, h->p.storage, ta, 0, h->stream);
             if (e != hipSuccess) return hip_fail(h, e, "in-place thermal step kernel launch");
             h->parity ^= 1;
         }
@@ -591,9 +591,9 @@ int lbm_step(lbm_t h, int nsteps)
     if (h->thermal) {
         ThermalArgs ta = thermal_args(h);
         for (int t = 0; t < nsteps; ++t) {
-            ta.src = static_cast<const float *>(h->buf[h->cur]);
-            ta.dst = static_cast<float *>(h->buf[h->cur ^ 1]);
-            const hipError_t e = launch_thermal(0, ta, 0, h->stream);
+            ta.src = h->buf[h->cur];
+            ta.dst = h->buf[h->cur ^ 1];
+            const hipError_t e = launch_thermal(0, h->p.storage, ta, 0, h->stream);
             if (e != hipSuccess) return hip_fail(h, e, "thermal step kernel launch");
             h->cur ^= 1;
         }
@@ -625,9 +625,9 @@ int lbm_step_from(lbm_t h, const void *src, void *dst)
     if (!src || !dst || src == dst) return fail(h, LBM_EINVAL, "src and dst must be distinct non-null buffers");
     if (h->thermal) {
         ThermalArgs ta = thermal_args(h);
-        ta.src = static_cast<const float *>(src);
-        ta.dst = static_cast<float *>(dst);
-        const hipError_t e = launch_thermal(0, ta, 0, h->stream);
+        ta.src = src;
+        ta.dst = dst;
+        const hipError_t e = launch_thermal(0, h->p.storage, ta, 0, h->stream);
         if (e != hipSuccess) return hip_fail(h, e, "thermal step kernel launch");
         return LBM_OK;
     }
@@ -646,14 +646,14 @@ int lbm_step_from(lbm_t h, const void *src, void *dst)
 static int thermal_gather(lbm_t h, const void *state, float *rho, float *u, float *tb, double *f64, double *parts)
 {
     ThermalArgs a = thermal_args(h);
-    a.src = static_cast<const float *>(state ? state : h->buf[h->cur]);
+    a.src = state ? state : h->buf[h->cur];
     a.odd = (!state && h->aa && h->parity) ? 1 : 0;
     a.out_rho = rho;
     a.out_u = u;
     a.out_tb = tb;
     a.f64 = f64;
     a.partials = parts;
-    const hipError_t e = launch_thermal(parts ? 4 : (f64 ? 3 : 2), a, kReduceBlocks, h->stream);
+    const hipError_t e = launch_thermal(parts ? 4 : (f64 ? 3 : 2), h->p.storage, a, kReduceBlocks, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "thermal gather kernel launch");
     return LBM_OK;
 }
@@ -792,9 +792,9 @@ int lbm_get_state(lbm_t h, void *dst)
         if (dst == h->buf[0]) return fail(h, LBM_EINVAL, "dst must not be the handle's own state buffer");
         if (h->thermal) {
             ThermalArgs ta = thermal_args(h);
-            ta.src = static_cast<const float *>(h->buf[0]);
-            ta.dst = static_cast<float *>(dst);
-            const hipError_t e = launch_thermal(7, ta, 0, h->stream);
+            ta.src = h->buf[0];
+            ta.dst = dst;
+            const hipError_t e = launch_thermal(7, h->p.storage, ta, 0, h->stream);
             if (e != hipSuccess) return hip_fail(h, e, "state layout kernel launch");
             return LBM_OK;
         }

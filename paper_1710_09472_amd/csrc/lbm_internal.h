@@ -155,6 +155,7 @@ struct AdjointArgs {
 struct ThermalPhysics {
     float omega;       // 1 / tau
     float rho0;
+    float scale, inv_scale;  // stored value = deviation * scale (2^k for FP16, else 1)
     float tb_hi, tb_lo;  // T = sum what e^2 = c_s^2 I_2 / I_0 (thetabar_e of the weight), two FP32 parts
     float g0;          // g held at the weight's value, I_4 I_0 / I_2^2
     float what[7];     // w / I_0 in the order e = 0, +1, -1, +2, -2, +3, -3
@@ -172,8 +173,8 @@ struct ThermalArgs {
     int n;             // nodes
     int stride;        // elements between population arrays
     ThermalPhysics ph;
-    const float *src;
-    float *dst;
+    const void *src;   // states: FP32, FP16 x 2^k or BF16 deviations (lbm_params.storage)
+    void *dst;
     const double *rho, *u, *tb;   // init fields (u, tb nullable)
     float *out_rho, *out_u, *out_tb;  // moment fields (nullable)
     double *f64;       // export (nullable)
@@ -183,7 +184,7 @@ struct ThermalArgs {
 
 // mode 0: step src -> dst; 1: init into dst; 2: fields; 3: export; 4: partial sums;
 // 5, 6: the two phases of the in-place step (src == dst); 7: odd layout src -> even dst
-hipError_t launch_thermal(int mode, const ThermalArgs &a, int nblocks_reduce, hipStream_t st);
+hipError_t launch_thermal(int mode, int storage, const ThermalArgs &a, int nblocks_reduce, hipStream_t st);
 
 // Launchers (lbm_kernels.hip). Each returns hipSuccess or the launch error.
 // force: 0 no field, 1 E only, 2 E and B.

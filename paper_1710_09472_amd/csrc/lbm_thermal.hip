@@ -106,15 +106,27 @@ __device__ __forceinline__ void thermal_moments(const float *d, float &drho, flo
     }
 }
 
+// Stored value of a deviation: FP32, FP16 x 2^k or BF16 (Codec); ld/st decode and encode.
+template <int ST>
+using TT = typename Codec<ST>::T;
+
+template <int ST>
+__device__ __forceinline__ float tload_nt(const TT<ST> *p, float inv_scale)
+{
+    return Codec<ST>::dec(__builtin_nontemporal_load(p), inv_scale);
+}
+
 // The pre-collision populations of node x: slot q of x - e_q (the layout the two-buffer
 // step leaves, "even"), or, after the pull phase of the in-place step ("odd"), slot qbar
 // of x itself.
+template <int ST>
 __device__ __forceinline__ void thermal_pull(const ThermalArgs &a, int x, float *d)
 {
+    const TT<ST> *src = static_cast<const TT<ST> *>(a.src);
 #pragma unroll
     for (int q = 0; q < kQ7; ++q)
-        d[q] = a.odd ? __builtin_nontemporal_load(at32(a.src + (size_t)kOpp7[q] * a.stride, (unsigned)x))
-                     : __builtin_nontemporal_load(at32(a.src + (size_t)q * a.stride, wrap_shift(x, kE7[q], a.n)));
+        d[q] = a.odd ? tload_nt<ST>(at32(src + (size_t)kOpp7[q] * a.stride, (unsigned)x), a.ph.inv_scale)
+                     : tload_nt<ST>(at32(src + (size_t)q * a.stride, wrap_shift(x, kE7[q], a.n)), a.ph.inv_scale);
 }
 
 // post-collision deviations of a node from its pre-collision ones
@@ -127,24 +139,29 @@ __device__ __forceinline__ void thermal_collide(const ThermalPhysics &p, const f
     for (int q = 0; q < kQ7; ++q) o[q] = __builtin_fmaf(p.omega, feq[q] - d[q], d[q]);
 }
 
+template <int ST>
 __global__ __launch_bounds__(kBlock) void k_thermal_step(ThermalArgs a)
 {
     const int x = (int)(blockIdx.x * kBlock + threadIdx.x);
     if (x >= a.n) return;
+    const TT<ST> *src = static_cast<const TT<ST> *>(a.src);
+    TT<ST> *dst = static_cast<TT<ST> *>(a.dst);
     float d[kQ7], o[kQ7];
     if (x >= 3 && x + 3 < a.n) {
         // no wrap: the rest population is read once (non-temporal); the shifted ones stay
         // cached, since the lines at a tile's edges are shared with the neighbouring tiles
         // (measured 2 % faster than non-temporal loads throughout)
-        d[0] = __builtin_nontemporal_load(at32(a.src, (unsigned)x));
+        d[0] = tload_nt<ST>(at32(src, (unsigned)x), a.ph.inv_scale);
 #pragma unroll
-        for (int q = 1; q < kQ7; ++q) d[q] = a.src[(size_t)q * a.stride + (unsigned)(x - kE7[q])];
+        for (int q = 1; q < kQ7; ++q)
+            d[q] = Codec<ST>::dec(src[(size_t)q * a.stride + (unsigned)(x - kE7[q])], a.ph.inv_scale);
     } else {
-        thermal_pull(a, x, d);
+        thermal_pull<ST>(a, x, d);
     }
     thermal_collide(a.ph, d, o);
 #pragma unroll
-    for (int q = 0; q < kQ7; ++q) __builtin_nontemporal_store(o[q], at32(a.dst + (size_t)q * a.stride, (unsigned)x));
+    for (int q = 0; q < kQ7; ++q)
+        __builtin_nontemporal_store(Codec<ST>::enc(o[q], a.ph.scale), at32(dst + (size_t)q * a.stride, (unsigned)x));
 }
 
 // In-place step (one buffer, the AA pattern), phase 0: pull as the two-buffer step does
@@ -152,55 +169,66 @@ __global__ __launch_bounds__(kBlock) void k_thermal_step(ThermalArgs a)
 // from, slot qbar of x + e_q; each node writes exactly the locations it read, which no
 // other node touches. The buffer then holds the streamed ("odd") layout: f_q(x) in slot
 // qbar of x.
+template <int ST>
 __global__ __launch_bounds__(kBlock) void k_thermal_aa_pull(ThermalArgs a)
 {
     const int x = (int)(blockIdx.x * kBlock + threadIdx.x);
     if (x >= a.n) return;
-    float *f = a.dst;
+    TT<ST> *f = static_cast<TT<ST> *>(a.dst);
     float d[kQ7], o[kQ7];
     const bool interior = x >= 3 && x + 3 < a.n;
 #pragma unroll
     for (int q = 0; q < kQ7; ++q)
-        d[q] = f[(size_t)q * a.stride + (interior ? (unsigned)(x - kE7[q]) : wrap_shift(x, kE7[q], a.n))];
+        d[q] = Codec<ST>::dec(f[(size_t)q * a.stride + (interior ? (unsigned)(x - kE7[q]) : wrap_shift(x, kE7[q], a.n))],
+                              a.ph.inv_scale);
     thermal_collide(a.ph, d, o);
 #pragma unroll
     for (int q = 0; q < kQ7; ++q)
-        __builtin_nontemporal_store(o[q], at32(f + (size_t)kOpp7[q] * a.stride,
-                                               interior ? (unsigned)(x + kE7[q]) : wrap_shift(x, -kE7[q], a.n)));
+        __builtin_nontemporal_store(Codec<ST>::enc(o[q], a.ph.scale),
+                                    at32(f + (size_t)kOpp7[q] * a.stride,
+                                         interior ? (unsigned)(x + kE7[q]) : wrap_shift(x, -kE7[q], a.n)));
 }
 
 // Phase 1: f_q(x) from slot qbar of x, collide, store g_q(x) in slot q of x (the
 // two-buffer layout again).
+template <int ST>
 __global__ __launch_bounds__(kBlock) void k_thermal_aa_local(ThermalArgs a)
 {
     const int x = (int)(blockIdx.x * kBlock + threadIdx.x);
     if (x >= a.n) return;
-    float *f = a.dst;
+    TT<ST> *f = static_cast<TT<ST> *>(a.dst);
     float d[kQ7], o[kQ7];
 #pragma unroll
-    for (int q = 0; q < kQ7; ++q) d[q] = __builtin_nontemporal_load(at32(f + (size_t)kOpp7[q] * a.stride, (unsigned)x));
+    for (int q = 0; q < kQ7; ++q) d[q] = tload_nt<ST>(at32(f + (size_t)kOpp7[q] * a.stride, (unsigned)x), a.ph.inv_scale);
     thermal_collide(a.ph, d, o);
 #pragma unroll
-    for (int q = 0; q < kQ7; ++q) __builtin_nontemporal_store(o[q], at32(f + (size_t)q * a.stride, (unsigned)x));
+    for (int q = 0; q < kQ7; ++q)
+        __builtin_nontemporal_store(Codec<ST>::enc(o[q], a.ph.scale), at32(f + (size_t)q * a.stride, (unsigned)x));
 }
 
-// Odd layout src -> even layout dst: g_q(y) = src slot qbar of y + e_q.
+// Odd layout src -> even layout dst: g_q(y) = src slot qbar of y + e_q (stored values moved
+// as they are).
+template <int ST>
 __global__ __launch_bounds__(kBlock) void k_thermal_canon(ThermalArgs a)
 {
     const int y = (int)(blockIdx.x * kBlock + threadIdx.x);
     if (y >= a.n) return;
+    const TT<ST> *src = static_cast<const TT<ST> *>(a.src);
+    TT<ST> *dst = static_cast<TT<ST> *>(a.dst);
 #pragma unroll
     for (int q = 0; q < kQ7; ++q)
-        a.dst[(size_t)q * a.stride + y] = a.src[(size_t)kOpp7[q] * a.stride + wrap_shift(y, -kE7[q], a.n)];
+        dst[(size_t)q * a.stride + y] = src[(size_t)kOpp7[q] * a.stride + wrap_shift(y, -kE7[q], a.n)];
 }
 
 // Initial state f = f^eq(rho, u, thetabar): the deviations of node x are stored where
-// the first pull reads them (slot a of x - e_a... i.e. of the node the pull into x reads).
+// the first pull into each node reads them, slot q of x - e_q.
+template <int ST>
 __global__ __launch_bounds__(kBlock) void k_thermal_init(ThermalArgs a)
 {
     const int x = (int)(blockIdx.x * kBlock + threadIdx.x);
     if (x >= a.n) return;
     const ThermalPhysics &p = a.ph;
+    TT<ST> *dst = static_cast<TT<ST> *>(a.dst);
     const double rho = a.rho[x];
     const double u = a.u ? a.u[x] * p.cs : 0.0;                         // lattice units
     const double tb = a.tb ? a.tb[x] * p.cs * p.cs : p.T;
@@ -211,19 +239,16 @@ __global__ __launch_bounds__(kBlock) void k_thermal_init(ThermalArgs a)
     float feq[kQ7];
     thermal_equilibrium(p, drho, j, dE, feq);
 #pragma unroll
-    for (int q = 0; q < kQ7; ++q) {
-        // the pull of q into node y reads slot q of y - e_q: node x's value goes to x
-        // itself only when e_q = 0; store f^eq_q(x) at slot q of x - e_q
-        a.dst[(size_t)q * a.stride + wrap_shift(x, kE7[q], a.n)] = feq[q];
-    }
+    for (int q = 0; q < kQ7; ++q) dst[(size_t)q * a.stride + wrap_shift(x, kE7[q], a.n)] = Codec<ST>::enc(feq[q], p.scale);
 }
 
+template <int ST>
 __global__ __launch_bounds__(kBlock) void k_thermal_fields(ThermalArgs a)
 {
     const int x = (int)(blockIdx.x * kBlock + threadIdx.x);
     if (x >= a.n) return;
     float d[kQ7], feq[kQ7];
-    thermal_pull(a, x, d);
+    thermal_pull<ST>(a, x, d);
     if (a.f64) {
 #pragma unroll
         for (int q = 0; q < kQ7; ++q) a.f64[(size_t)q * a.n + x] = a.ph.what_rho0[q] + (double)d[q];
@@ -240,12 +265,13 @@ __global__ __launch_bounds__(kBlock) void k_thermal_fields(ThermalArgs a)
 }
 
 // Per-block FP64 sums of (drho, j, dE), lattice units, over a grid-stride range of nodes.
+template <int ST>
 __global__ __launch_bounds__(kBlock) void k_thermal_partials(ThermalArgs a)
 {
     double acc[3] = {0.0, 0.0, 0.0};
     for (int x = (int)(blockIdx.x * kBlock + threadIdx.x); x < a.n; x += (int)(gridDim.x * kBlock)) {
         float d[kQ7];
-        thermal_pull(a, x, d);
+        thermal_pull<ST>(a, x, d);
         float drho, j, dE;
         thermal_moments(d, drho, j, dE);
         acc[0] += drho;
@@ -265,45 +291,54 @@ __global__ __launch_bounds__(kBlock) void k_thermal_partials(ThermalArgs a)
     }
 }
 
-}  // namespace
-
-hipError_t launch_thermal(int mode, const ThermalArgs &a, int nblocks_reduce, hipStream_t st)
+template <int ST>
+hipError_t launch_thermal_st(int mode, const ThermalArgs &a, int nblocks_reduce, hipStream_t st)
 {
     const dim3 block(kBlock), grid((a.n + kBlock - 1) / kBlock);
     switch (mode) {
     case 0:
         if (!a.src || !a.dst || a.src == a.dst) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_thermal_step, grid, block, 0, st, a);
+        hipLaunchKernelGGL(k_thermal_step<ST>, grid, block, 0, st, a);
         break;
     case 1:
         if (!a.dst || !a.rho) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_thermal_init, grid, block, 0, st, a);
+        hipLaunchKernelGGL(k_thermal_init<ST>, grid, block, 0, st, a);
         break;
     case 2:
     case 3:
         if (!a.src) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_thermal_fields, grid, block, 0, st, a);
+        hipLaunchKernelGGL(k_thermal_fields<ST>, grid, block, 0, st, a);
         break;
     case 4:
         if (!a.src || !a.partials || nblocks_reduce < 1) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_thermal_partials, dim3(nblocks_reduce), block, 0, st, a);
+        hipLaunchKernelGGL(k_thermal_partials<ST>, dim3(nblocks_reduce), block, 0, st, a);
         break;
     case 5:
     case 6:
         if (!a.dst || a.src != a.dst) return hipErrorInvalidValue;
         if (mode == 5)
-            hipLaunchKernelGGL(k_thermal_aa_pull, grid, block, 0, st, a);
+            hipLaunchKernelGGL(k_thermal_aa_pull<ST>, grid, block, 0, st, a);
         else
-            hipLaunchKernelGGL(k_thermal_aa_local, grid, block, 0, st, a);
+            hipLaunchKernelGGL(k_thermal_aa_local<ST>, grid, block, 0, st, a);
         break;
     case 7:
         if (!a.src || !a.dst || a.src == a.dst) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_thermal_canon, grid, block, 0, st, a);
+        hipLaunchKernelGGL(k_thermal_canon<ST>, grid, block, 0, st, a);
         break;
     default:
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_thermal(int mode, int storage, const ThermalArgs &a, int nblocks_reduce, hipStream_t st)
+{
+    if (storage == LBM_F32) return launch_thermal_st<LBM_F32>(mode, a, nblocks_reduce, st);
+    if (storage == LBM_F16) return launch_thermal_st<LBM_F16>(mode, a, nblocks_reduce, st);
+    if (storage == LBM_BF16) return launch_thermal_st<LBM_BF16>(mode, a, nblocks_reduce, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace lbm

@@ -222,7 +222,7 @@ def test_d1v7_constants_match_the_oracle(stats, theta, mu):
 def test_thermal_model_validation_without_device_work():
     assert _rc(lbm.make_params("D1V7", 64, 2)) == lbm.LBM_EINVAL                 # ny must be 1
     assert _rc(lbm.make_params("D1V7", 64, E=(1e-6, 0, 0))) == lbm.LBM_EINVAL     # no fields
-    assert _rc(lbm.make_params("D1V7", 64, storage="f16")) == lbm.LBM_EUNSUPPORTED
+    assert _rc(lbm.make_params("D1V7", 64, storage="f16", dev_scale_log2=17)) == lbm.LBM_OK
     assert _rc(lbm.make_params("D1V7", 64)) == lbm.LBM_OK
     assert _rc(lbm.make_params("D1V7", 64, order=3)) == lbm.LBM_OK
     assert _rc(lbm.make_params("D1V7", 64, order=4)) == lbm.LBM_OK

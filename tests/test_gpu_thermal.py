@@ -42,9 +42,9 @@ def _oracle(n, tau, regime, K=4):
     return ThermalOracle(n, tau, theta=theta, mu=mu, stats=STATS.get(regime, "fd"), K=K)
 
 
-def _sim(wl, tau=None, order=0, inplace=False, stats="fd"):
+def _sim(wl, tau=None, order=0, inplace=False, stats="fd", storage="f32", k=0):
     sim = lbm.Simulation("D1V7", wl.nx, 1, 1, tau=tau or wl.tau, theta=wl.theta, mu=wl.mu, order=order,
-                         inplace=inplace, stats=stats)
+                         inplace=inplace, stats=stats, storage=storage, dev_scale_log2=k)
     sim.init(wl.rho, wl.u, wl.thetabar)
     return sim
 
@@ -135,6 +135,36 @@ def test_thermal_bose_einstein_weight(n, steps, K):
     Mo, Po, Eo = m.totals(f)
     cur, E = sim.current(), sim.energy()
     assert abs(cur[0] / Mo - 1) < 1e-6 and abs(E / Eo - 1) < 1e-6 and abs(cur[1] - Po) < 1e-6 * Mo
+
+
+# 16-bit storage: stated bars on the errors against the FP64 oracle (max errors relative to
+# max|rho|, max|u|, max|thetabar - thetabar_ref|), a few times above the measured ones
+# (FP16 x 2^17: rho 3-4e-6, u 0.7-1.2e-3, thetabar 0.8-1.0e-3; BF16: rho 3-4e-5,
+# u 5.6-8.5e-3, thetabar 6.9-7.7e-3; mass drift 1.7e-7 and 0.2-1.2e-6)
+BARS16 = {"f16": (2e-5, 5e-3, 5e-3), "bf16": (2e-4, 5e-2, 5e-2)}
+
+
+@pytest.mark.parametrize("storage,k", [("f16", 17), ("bf16", 0)])
+@pytest.mark.parametrize("n,steps", [(1000, 40), (300, 200)])
+def test_thermal_16bit_storage(storage, k, n, steps):
+    """Deviations stored in FP16 x 2^17 or BF16, FP32 arithmetic: errors against the oracle
+    (printed, bounded by BARS16), the in-place step bit for bit the two-buffer step, and
+    the mass drift of 16-bit rounding (the stored deviations are rounded each step)."""
+    m = _oracle(n, 0.8, "degenerate")
+    wl = W.thermal_1d(m.thetabar_ref, n=n, seed=51 + n)
+    sim = _sim(wl, storage=storage, k=k)
+    one = _sim(wl, storage=storage, k=k, inplace=True)
+    M0 = sim.current()[0]
+    sim.step(steps)
+    one.step(steps)
+    f = m.run(m.init_state(wl.rho, wl.u[0], wl.thetabar), steps)
+    er, eu, et = _errors(_state_fields(sim, m), m.macro(f), m.thetabar_ref)
+    dm = abs(sim.current()[0] / M0 - 1)
+    print(f"{storage} n={n} steps={steps}: rho {er:.2e} u {eu:.2e} thetabar {et:.2e}; mass drift {dm:.2e}")
+    br, bu, bt = BARS16[storage]
+    assert er < br and eu < bu and et < bt, (er, eu, et)
+    assert torch.equal(one.export_f64(), sim.export_f64())
+    assert torch.equal(one.get_state(), sim.get_state())
 
 
 @pytest.mark.parametrize("steps", [0, 1, 24, 25])
