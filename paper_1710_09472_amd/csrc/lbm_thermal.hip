@@ -54,7 +54,7 @@ __device__ __forceinline__ ThermalNode thermal_equilibrium(const ThermalPhysics 
 #pragma clang fp contract(off)  // every fused multiply-add is explicit: the same bits in every kernel
     ThermalNode m;
     m.rho = p.rho0 + drho;
-    const float inv = 1.0f / m.rho;
+    const float inv = __builtin_amdgcn_rcpf(m.rho);  // v_rcp_f32 (1 ulp), as in the isothermal step
     m.u = j * inv;
     const float u2 = m.u * m.u;
     // D = dE - T drho = rho (thetabar - T) + rho u^2   (sum rho0 what e^2 = rho0 T)
