@@ -239,9 +239,10 @@ int lbm_set_tau(lbm_t h, double tau);
  * lbm_adjoint_step are discarded. Async. */
 int lbm_adjoint_seed(lbm_t h, int axis, double norm, float *lam);
 
-/* One reverse step of the discrete adjoint of lbm_step (not in the paper), for the
- * source forcing and bounce-back walls: LBM_EUNSUPPORTED with LBM_FORCE_SHIFT or slip
- * walls (as lbm_adjoint_seed).
+/* One reverse step of the discrete adjoint of lbm_step (not in the paper), for either
+ * forcing (the source of Eq. 31, or the velocity shift of Sec. 9.3, Eq. 34) and
+ * bounce-back walls: LBM_EUNSUPPORTED with free-slip walls or the D1V7 thermal model
+ * (as lbm_adjoint_seed).
  *   state   : the state buffer whose populations are pre-collision at step t (what the
  *             handle held before the forward step t -> t+1)
  *   lam_in  : dJ/df(t+1) (adjoint_bytes); lam_out: dJ/df(t) (distinct buffer)

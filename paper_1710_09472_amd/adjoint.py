@@ -10,7 +10,8 @@ checkpoint-and-recompute: the forward pass keeps the state every K steps; the ba
 pass restores each checkpoint, recomputes the K states of that segment with
 ``lbm_step_from`` and walks them in reverse. Gradients: dJ/dE (3), dJ/dtau and the
 field dJ/ds of the partial bounce-back fraction. All arithmetic runs in the library's
-kernels; this module only orders the calls and owns the buffers (torch tensors).
+kernels; this module only orders the calls and owns the buffers (torch tensors). Both
+forcing schemes are covered (``Problem.forcing``); free-slip walls are not.
 """
 from __future__ import annotations
 
@@ -35,6 +36,7 @@ class Problem:
     B: tuple = (0.0, 0.0, 0.0)
     checkpoint: int = 50
     axis: int = 0
+    forcing: str = "source"         # "source" (Eq. 31) or "shift" (Sec. 9.3)
 
     @property
     def N(self):
@@ -43,7 +45,7 @@ class Problem:
 
 def _make_sim(pb: Problem, E, tau, s):
     return Simulation(pb.lattice, pb.nx, pb.ny, pb.nz, tau=float(tau), E=[float(v) for v in E], B=pb.B,
-                      mask=pb.mask, s=s)
+                      mask=pb.mask, s=s, forcing=pb.forcing)
 
 
 def forward_with_checkpoints(pb: Problem, E, tau, s):

@@ -207,7 +207,8 @@ hipError_t launch_reduce_final(const double *partials, int nparts, int ncomp, do
                                int accumulate, hipStream_t st, double *stage);
 int step_vector_width(int lattice, int storage, int nx);
 int use_xcd_remap(int lattice, bool mask, bool soft);
-hipError_t launch_adjoint(int lattice, int storage, bool mag, const AdjointArgs &a, hipStream_t st);
+// shift: the adjoint of the velocity-shift forcing (k_adjoint_shift), else of the source
+hipError_t launch_adjoint(int lattice, int storage, bool mag, bool shift, const AdjointArgs &a, hipStream_t st);
 // In-place step (lbm_aa.hip), a.src == a.dst: phase 0 takes the state from the two-buffer
 // layout to the odd layout, phase 1 back. launch_canon writes the two-buffer layout of an
 // odd-layout state a.src into a.dst (a distinct buffer).

@@ -557,6 +557,168 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
         for (int c = 0; c < 4; ++c) part[c] = prev[c] + acc[c];
 }
 
+// ---------------------------------------------------------------------------------
+// K5 for the velocity shift (eq. u-update-force-term-eq: f^eq at u + tau (E + u x B), no
+// source term). In lattice units with j = sum d e, the shifted momentum is
+//   j' = j + rho tau c_s E + tau (j x B),   U' = j' / (c_s^2 rho),
+// and f*_q = d_q + omega (deq_q(drho, j') - d_q) with deq_q = what_k drho + lam_k e.j'
+// + what_k rho (Bc (e.U')^2 + Cp_k U'^2), the rest population by mass closure. With
+// hbar = (1 - s) gbar and eta_q = hbar_q - hbar_0 (q != 0):
+//   G = omega sum eta_q [lam_k e_q + 2 what_k (Bc (e.U') e_q + Cp_k U') / c_s^2]  (d/dj')
+//   C = omega sum eta_q (what_k - Q_q / rho) + tau c_s G.E,  Q_q = what_k rho (Bc (e.U')^2
+//       + Cp_k U'^2)
+//   lam_out_b = (1 - omega) hbar_b + omega hbar_0 + C + e_b . (G + tau B x G) + s gbar_bbar
+//   dJ/dE += rho tau c_s G;  dJ/dtau += omega^2 sum eta_q (d_q - deq_q) + G.(rho c_s E + j x B);
+//   dJ/ds += sum_q gbar_q (d_qbar - f*_q).
+// ---------------------------------------------------------------------------------
+template <int LAT, int ST, bool MASK, bool SOFT, bool MAG>
+__global__ __launch_bounds__(kBlock) void k_adjoint_shift(AdjointArgs a)
+{
+    using L = Lat<LAT>;
+    using T = typename Codec<ST>::T;
+    using LT = typename LinkMask<LAT>::T;
+    const Geometry &g = a.g;
+    const Physics &p = a.ph;
+    const int bid = a.remap ? xcd_remap((int)blockIdx.x, g.nblocks) : (int)blockIdx.x;
+    const Tile t = tile_of(g, bid);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool last_lane = (threadIdx.x & 63) == 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    double *part = a.partials + ((size_t)blockIdx.x * (kBlock / 64) + wave) * 4;
+    if ((bid - fast_div(bid, g.div_ntx) * g.ntx) * kBlock + wave * 64 >= g.nx) {
+        if (!a.accumulate && last_lane)
+            for (int c = 0; c < 4; ++c) part[c] = 0.0;
+        return;
+    }
+    double prev[4] = {0.0, 0.0, 0.0, 0.0};
+    if (a.accumulate)
+        for (int c = 0; c < 4; ++c) prev[c] = part[c];
+    const float gs_prev = (SOFT && a.grad_s && t.valid) ? *at32(a.grad_s, (unsigned)t.own) : 0.f;
+    LT lk[1] = {0};
+    bool solid = false;
+    if (MASK && t.valid) {
+        lk[0] = *at32(static_cast<const LT *>(a.links), (unsigned)t.own);
+        solid = (lk[0] & LinkMask<LAT>::solid) != 0;
+    }
+    if (t.valid && solid) {
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) *at32(a.lam_out + (size_t)q * g.stride, (unsigned)t.own) = 0.f;
+    } else if (t.valid) {
+        float d[1][L::Q], gb[L::Q];
+        gather_tile<LAT, ST, MASK, 1>(g, static_cast<const T *>(a.state), p.inv_scale, t, lk, d);
+        {
+            const int xm = wrapm(t.x0, g.nx), xp = wrapp(t.x0, g.nx);
+            const int ym = wrapm(t.y, g.ny), yp = wrapp(t.y, g.ny);
+            const int zm = wrapm(t.z, g.nz), zp = wrapp(t.z, g.nz);
+#pragma unroll
+            for (int q = 0; q < L::Q; ++q) {
+                const unsigned tx = (unsigned)(L::ex[q] > 0 ? xp : (L::ex[q] < 0 ? xm : t.x0));
+                const int ty = L::ey[q] > 0 ? yp : (L::ey[q] < 0 ? ym : t.y);
+                const int tz = L::ez[q] > 0 ? zp : (L::ez[q] < 0 ? zm : t.z);
+                const float *lq = a.lam_in + (size_t)q * g.stride;
+                float v = *at32(lq + (size_t)g.nx * (ty + g.ny * tz), tx);
+                if (MASK && q != 0 && ((lk[0] >> L::opp[q]) & 1u))
+                    v = *at32(a.lam_in + (size_t)L::opp[q] * g.stride, (unsigned)t.own);
+                gb[q] = v;
+            }
+        }
+        const float s = SOFT ? *at32(g.s, (unsigned)t.own) : 0.f;
+        const Macro<LAT> m = macro<LAT>(p, d[0]);
+        const float om = p.omega;
+        const float tau = 1.f / om;
+        const float inv_rho = __builtin_amdgcn_rcpf(m.rho);
+        const float one_s = 1.f - s;
+        // shifted momentum j' and velocity U'
+        float jxB[3] = {0.f, 0.f, 0.f}, jp[3], Up[3];
+        if (MAG) {
+            jxB[0] = m.j[1] * p.B[2] - m.j[2] * p.B[1];
+            jxB[1] = m.j[2] * p.B[0] - m.j[0] * p.B[2];
+            jxB[2] = m.j[0] * p.B[1] - m.j[1] * p.B[0];
+        }
+        const float kk = p.inv_cs2 * inv_rho;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            jp[i] = m.j[i] + tau * (m.rho * p.cs * p.E[i] + jxB[i]);
+            Up[i] = jp[i] * kk;
+        }
+        if (L::D == 2) {
+            jp[2] = 0.f;
+            Up[2] = 0.f;
+        }
+        const float U2 = Up[0] * Up[0] + Up[1] * Up[1] + Up[2] * Up[2];
+        const float h0 = one_s * gb[0];
+        float Ge[3] = {0.f, 0.f, 0.f};
+        float Sc = 0.f, Cs = 0.f, dtau = 0.f, ds = 0.f, sum_eq = 0.f;
+        auto acc_e = [](float *acc3, float v, int ex, int ey, int ez) {
+            if (ex) acc3[0] += ex > 0 ? v : -v;
+            if (ey) acc3[1] += ey > 0 ? v : -v;
+            if (ez) acc3[2] += ez > 0 ? v : -v;
+        };
+        for_q<L::Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            if constexpr (q != 0) {
+                constexpr int k = shell<LAT, q>();
+                constexpr int ex = L::ex[q], ey = L::ey[q], ez = L::ez[q];
+                const float eu = edot<LAT, q>(Up);
+                const float ej = edot<LAT, q>(jp);
+                const float quad = __builtin_fmaf(p.Bc * eu, eu, p.Cp[k] * U2);
+                const float Qq = p.what[k] * m.rho * quad;
+                const float deq = __builtin_fmaf(p.lam[k], ej, p.what[k] * m.drho) + Qq;
+                sum_eq += deq;
+                const float eta = one_s * gb[q] - h0;
+                acc_e(Ge, eta * (p.lam[k] + 2.f * p.what[k] * p.inv_cs2 * p.Bc * eu), ex, ey, ez);
+                Sc = __builtin_fmaf(eta, 2.f * p.what[k] * p.inv_cs2 * p.Cp[k], Sc);
+                Cs = __builtin_fmaf(eta, p.what[k] - Qq * inv_rho, Cs);
+                dtau = __builtin_fmaf(eta, d[0][q] - deq, dtau);
+                if (SOFT) {
+                    const float fst = __builtin_fmaf(om, deq - d[0][q], d[0][q]);
+                    ds = __builtin_fmaf(gb[q], d[0][L::opp[q]] - fst, ds);
+                }
+            }
+        });
+        if (SOFT) {
+            const float deq0 = m.drho - sum_eq;
+            const float fst0 = __builtin_fmaf(om, deq0 - d[0][0], d[0][0]);
+            ds = __builtin_fmaf(gb[0], d[0][0] - fst0, ds);
+        }
+        float G[3], H[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) G[i] = om * __builtin_fmaf(Sc, Up[i], Ge[i]);
+        if (L::D == 2) G[2] = 0.f;
+        const float GE = G[0] * p.E[0] + G[1] * p.E[1] + G[2] * p.E[2];
+        const float C = __builtin_fmaf(om, Cs, tau * p.cs * GE);
+        H[0] = G[0];
+        H[1] = G[1];
+        H[2] = G[2];
+        if (MAG) {  // + tau B x G
+            H[0] += tau * (p.B[1] * G[2] - p.B[2] * G[1]);
+            H[1] += tau * (p.B[2] * G[0] - p.B[0] * G[2]);
+            H[2] += tau * (p.B[0] * G[1] - p.B[1] * G[0]);
+        }
+        const float base = __builtin_fmaf(om, h0, C);
+        const float one_om = 1.f - om;
+        for_q<L::Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            float out = __builtin_fmaf(one_om, one_s * gb[q], base + edot<LAT, q>(H));
+            if (SOFT) out = __builtin_fmaf(s, gb[L::opp[q]], out);
+            *at32(a.lam_out + (size_t)q * g.stride, (unsigned)t.own) = out;
+        });
+        if (SOFT && a.grad_s) *at32(a.grad_s, (unsigned)t.own) = gs_prev + ds;
+        const float rtc = m.rho * tau * p.cs;
+        acc[0] = (double)(rtc * G[0]);
+        acc[1] = (double)(rtc * G[1]);
+        acc[2] = (double)(rtc * G[2]);
+        float Gt = 0.f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) Gt = __builtin_fmaf(G[i], m.rho * p.cs * p.E[i] + jxB[i], Gt);
+        acc[3] = (double)(om * om) * (double)dtau + (double)Gt;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = wave_sum_last_lane(acc[c]);
+    if (last_lane)
+        for (int c = 0; c < 4; ++c) part[c] = prev[c] + acc[c];
+}
+
 // Adjoint seed: lam(a, n) = e_a[axis] * value at fluid nodes (value = 1/(c_s norm)).
 template <int LAT>
 __global__ __launch_bounds__(kBlock) void k_seed(Geometry g, float value, int axis, float *lam)
@@ -613,11 +775,17 @@ hipError_t step_lat_st(int force, const StepArgs &a, hipStream_t st)
 }
 
 template <int LAT, int ST>
-hipError_t adjoint_lat_st(bool mag, const AdjointArgs &a, hipStream_t st)
+hipError_t adjoint_lat_st(bool mag, bool shift, const AdjointArgs &a, hipStream_t st)
 {
     const bool mask = a.links != nullptr, soft = a.g.s != nullptr;
     const dim3 grid(a.g.nblocks), block(kBlock);
-#define LBM_ADJ(M, S, B) hipLaunchKernelGGL((k_adjoint<LAT, ST, M, S, B>), grid, block, 0, st, a)
+#define LBM_ADJ(M, S, B)                                                                  \
+    do {                                                                                  \
+        if (shift)                                                                        \
+            hipLaunchKernelGGL((k_adjoint_shift<LAT, ST, M, S, B>), grid, block, 0, st, a); \
+        else                                                                              \
+            hipLaunchKernelGGL((k_adjoint<LAT, ST, M, S, B>), grid, block, 0, st, a);       \
+    } while (0)
     if (mask) {
         if (soft) {
             if (mag) LBM_ADJ(true, true, true); else LBM_ADJ(true, true, false);
@@ -683,9 +851,9 @@ hipError_t launch_step(int lattice, int storage, int force, const StepArgs &a, h
     LBM_DISPATCH(step_lat_st, force, a, st);
 }
 
-hipError_t launch_adjoint(int lattice, int storage, bool mag, const AdjointArgs &a, hipStream_t st)
+hipError_t launch_adjoint(int lattice, int storage, bool mag, bool shift, const AdjointArgs &a, hipStream_t st)
 {
-    LBM_DISPATCH(adjoint_lat_st, mag, a, st);
+    LBM_DISPATCH(adjoint_lat_st, mag, shift, a, st);
 }
 
 hipError_t launch_gather(int lattice, int storage, const GatherArgs &a, int nblocks_reduce, hipStream_t st)
