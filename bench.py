@@ -188,14 +188,14 @@ def thermal_extra(steps: int, warmup: int):
                         "achieved_GBs": round(alg / (e1 / steps) / 1e9, 1), "state_buffers": 1}}
 
 
-def adjoint_ratio(wl, steps: int, warmup: int):
+def adjoint_ratio(wl, steps: int, warmup: int, forcing: str = "source"):
     """Average time of one adjoint step (reverse pull, transposed collision and force,
     FP64 per-wave partials of dJ/dE and dJ/dtau held across steps and reduced on the
-    last one) relative to one forward step."""
+    last one) relative to one forward step of the same forcing."""
     import torch
     from paper_1710_09472_amd.lbm import Simulation
 
-    sim = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=(1e-6, 0, 0))
+    sim = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=(1e-6, 0, 0), forcing=forcing)
     sim.init(wl.rho)
     state = sim.get_state()
     lam = [sim.adjoint_seed(), sim.new_adjoint()]
@@ -421,11 +421,13 @@ def main():
                             "achieved_GBs": round(bytes_per_node(s16.Q, 2) * N / t16 / 1e9, 1),
                             "dev_scale_log2": k}
             s16.close()
-        t_adj, t_fwd = adjoint_ratio(wl, max(20, args.steps // 4), 5)
-        extras["adjoint"] = {"step_only_4096sq": {"ms_per_step": round(t_adj * 1e3, 5),
-                                                  "forward_ms_per_step": round(t_fwd * 1e3, 5),
-                                                  "ratio_to_forward": round(t_adj / t_fwd, 3)},
-                             "checkpointed_128cube": adjoint_pipeline()}
+        extras["adjoint"] = {}
+        for key, forcing in (("step_only_4096sq", "source"), ("step_only_4096sq_shift", "shift")):
+            t_adj, t_fwd = adjoint_ratio(wl, max(20, args.steps // 4), 5, forcing)
+            extras["adjoint"][key] = {"ms_per_step": round(t_adj * 1e3, 5),
+                                      "forward_ms_per_step": round(t_fwd * 1e3, 5),
+                                      "ratio_to_forward": round(t_adj / t_fwd, 3)}
+        extras["adjoint"]["checkpointed_128cube"] = adjoint_pipeline()
         extras["inplace"] = {"f32": inplace_extra(wl, "f32", 0, args.steps, args.warmup),
                              "f16": inplace_extra(wl, "f16", F16_SCALE["throughput_2d"], args.steps, args.warmup)}
         extras["thermal"] = thermal_extra(args.steps, args.warmup)
