@@ -234,15 +234,16 @@ int lbm_set_fields(lbm_t h, const double E[3], const double B[3]);
 int lbm_set_tau(lbm_t h, double tau);
 
 /* Adjoint seed for J = (1/norm) sum over fluid nodes x and a of f_a(x, T) xi_a[axis]:
- * lam[a*stride + n] = xi_a[axis]/norm at fluid nodes, 0 at solids. lam: device float
+ * lam[a*stride + n] = xi_a[axis]/norm at fluid nodes, 0 at solids (obstacles and free-slip
+ * wall planes). LBM_EUNSUPPORTED for the D1V7 thermal model. lam: device float
  * buffer of adjoint_bytes. Starts a reverse pass: held dJ/dE, dJ/dtau contributions of
  * lbm_adjoint_step are discarded. Async. */
 int lbm_adjoint_seed(lbm_t h, int axis, double norm, float *lam);
 
 /* One reverse step of the discrete adjoint of lbm_step (not in the paper), for either
- * forcing (the source of Eq. 31, or the velocity shift of Sec. 9.3, Eq. 34) and
- * bounce-back walls: LBM_EUNSUPPORTED with free-slip walls or the D1V7 thermal model
- * (as lbm_adjoint_seed).
+ * forcing (the source of Eq. 31, or the velocity shift of Sec. 9.3, Eq. 34), bounce-back
+ * obstacles, partial bounce-back and the free-slip wall planes of Sec. 9.4:
+ * LBM_EUNSUPPORTED for the D1V7 thermal model (as lbm_adjoint_seed).
  *   state   : the state buffer whose populations are pre-collision at step t (what the
  *             handle held before the forward step t -> t+1)
  *   lam_in  : dJ/df(t+1) (adjoint_bytes); lam_out: dJ/df(t) (distinct buffer)

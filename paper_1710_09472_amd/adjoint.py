@@ -11,7 +11,8 @@ pass restores each checkpoint, recomputes the K states of that segment with
 ``lbm_step_from`` and walks them in reverse. Gradients: dJ/dE (3), dJ/dtau and the
 field dJ/ds of the partial bounce-back fraction. All arithmetic runs in the library's
 kernels; this module only orders the calls and owns the buffers (torch tensors). Both
-forcing schemes are covered (``Problem.forcing``); free-slip walls are not.
+forcing schemes (``Problem.forcing``) and the free-slip wall planes (``Problem.slip``)
+are covered; J and the seed exclude the wall planes, which are solid.
 """
 from __future__ import annotations
 
@@ -37,6 +38,7 @@ class Problem:
     checkpoint: int = 50
     axis: int = 0
     forcing: str = "source"         # "source" (Eq. 31) or "shift" (Sec. 9.3)
+    slip: int = 0                   # free-slip wall planes (Sec. 9.4): bit 0 y, bit 1 z
 
     @property
     def N(self):
@@ -45,7 +47,7 @@ class Problem:
 
 def _make_sim(pb: Problem, E, tau, s):
     return Simulation(pb.lattice, pb.nx, pb.ny, pb.nz, tau=float(tau), E=[float(v) for v in E], B=pb.B,
-                      mask=pb.mask, s=s, forcing=pb.forcing)
+                      mask=pb.mask, s=s, forcing=pb.forcing, slip=pb.slip)
 
 
 def forward_with_checkpoints(pb: Problem, E, tau, s):

@@ -280,7 +280,7 @@ int force_level(const lbm_t h)
 // link masks exist where there are solids: obstacles of the mask, or slip wall planes
 bool has_solids(const lbm_t h) { return h->mask != nullptr || h->p.slip != 0; }
 const void *links_of(const lbm_t h) { return has_solids(h) ? h->links : nullptr; }
-bool adjoint_supported(const lbm_t h) { return h->p.slip == 0 && !h->thermal; }
+bool adjoint_supported(const lbm_t h) { return !h->thermal; }
 
 // Constants of the thermal kernel (D1V7) from the weights: what, xi, the weight's
 // thetabar and g, and the inverses of the even and odd blocks of the Hankel matrix of the
@@ -865,7 +865,7 @@ int lbm_adjoint_seed(lbm_t h, int axis, double norm, float *lam)
     if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
     if (!lam) return fail(h, LBM_EINVAL, "lam is required");
     if (!adjoint_supported(h))
-        return fail(h, LBM_EUNSUPPORTED, "the adjoint covers bounce-back walls (no free-slip planes) and the isothermal model");
+        return fail(h, LBM_EUNSUPPORTED, "the adjoint covers the isothermal model only");
     if (axis < 0 || axis >= h->D) return fail(h, LBM_EINVAL, "axis must be in 0..D-1");
     if (!(norm != 0.0) || !std::isfinite(norm)) return fail(h, LBM_EINVAL, "norm must be finite and non-zero");
     const hipError_t e = launch_seed(h->p.lattice, h->g, (float)(1.0 / (h->k.cs * norm)), axis, lam, h->stream);
@@ -881,7 +881,7 @@ int lbm_adjoint_step(lbm_t h, const void *state, const float *lam_in, float *lam
     if (!state || !lam_in || !lam_out) return fail(h, LBM_EINVAL, "state, lam_in and lam_out are required");
     if (lam_in == lam_out) return fail(h, LBM_EINVAL, "lam_in and lam_out must be distinct buffers");
     if (!adjoint_supported(h))
-        return fail(h, LBM_EUNSUPPORTED, "the adjoint covers bounce-back walls (no free-slip planes) and the isothermal model");
+        return fail(h, LBM_EUNSUPPORTED, "the adjoint covers the isothermal model only");
     AdjointArgs a{};
     a.g = h->g;
     a.ph = h->ph;

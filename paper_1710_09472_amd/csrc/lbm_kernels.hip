@@ -374,10 +374,46 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
     }
 }
 
+// dJ/dg_q(x) for every q of the fluid node of tile t: lam_in at the node and slot that
+// pull g_q(x) in the forward step (the transpose of pull_row): slot q of x + e_q; where
+// x + e_q lies in a free-slip wall plane, slot reflected(q) of x + e_q with the wall-axis
+// coordinates of x; where that destination is an obstacle (link bit qbar of x: the pull
+// of qbar into x bounces), slot qbar of x itself.
+template <int LAT, bool MASK>
+__device__ __forceinline__ void adjoint_pull(const Geometry &g, const Tile &t, const float *__restrict__ lam_in,
+                                             typename LinkMask<LAT>::T lk, float (&gb)[Lat<LAT>::Q])
+{
+    using L = Lat<LAT>;
+    const int xm = wrapm(t.x0, g.nx), xp = wrapp(t.x0, g.nx);
+    const int ym = wrapm(t.y, g.ny), yp = wrapp(t.y, g.ny);
+    const int zm = wrapm(t.z, g.nz), zp = wrapp(t.z, g.nz);
+    for_q<L::Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const unsigned tx = (unsigned)(L::ex[q] > 0 ? xp : (L::ex[q] < 0 ? xm : t.x0));
+        int ty = L::ey[q] > 0 ? yp : (L::ey[q] < 0 ? ym : t.y);
+        int tz = L::ez[q] > 0 ? zp : (L::ez[q] < 0 ? zm : t.z);
+        int p = q;
+        if (g.slip) {
+            const bool fy = L::ey[q] != 0 && (g.slip & LBM_SLIP_Y) && (ty == 0 || ty == g.ny - 1);
+            const bool fz = L::ez[q] != 0 && (g.slip & LBM_SLIP_Z) && (tz == 0 || tz == g.nz - 1);
+            if (fy) ty = t.y;
+            if (fz) tz = t.z;
+            constexpr int py = reflected<LAT>(q, true, false), pz = reflected<LAT>(q, false, true);
+            constexpr int pyz = reflected<LAT>(q, true, true);
+            p = fy ? (fz ? pyz : py) : (fz ? pz : q);
+        }
+        float v = *at32(lam_in + (size_t)p * g.stride + (size_t)g.nx * (ty + g.ny * tz), tx);
+        if constexpr (MASK && q != 0)
+            if ((lk >> L::opp[q]) & 1u) v = *at32(lam_in + (size_t)L::opp[q] * g.stride, (unsigned)t.own);
+        gb[q] = v;
+    });
+}
+
 // ---------------------------------------------------------------------------------
 // K5: one reverse step of the discrete adjoint. lam_out = dJ/df(t) from
 // lam_in = dJ/df(t+1); f(t) is pulled from the stored state as in K1.
-//   gbar_a = lam_in(x + e_a, a), or lam_in(x, abar) if x + e_a is solid;
+//   gbar_a = lam_in(x + e_a, a), or lam_in(x, abar) if x + e_a is solid (beside a free-slip
+//   wall plane: the specular destination, adjoint_pull);
 //   hbar_a = (1 - s) gbar_a;
 //   dJ/ds  += sum_a gbar_a (d_abar - d*_a);
 //   dJ/dtau += omega^2 sum_a hbar_a (d_a - deq_a);
@@ -426,23 +462,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
     } else if (t.valid) {
         float d[1][L::Q], gb[L::Q];
         gather_tile<LAT, ST, MASK, 1>(g, static_cast<const T *>(a.state), p.inv_scale, t, lk, d);
-        {
-            const int xm = wrapm(t.x0, g.nx), xp = wrapp(t.x0, g.nx);
-            const int ym = wrapm(t.y, g.ny), yp = wrapp(t.y, g.ny);
-            const int zm = wrapm(t.z, g.nz), zp = wrapp(t.z, g.nz);
-#pragma unroll
-            for (int q = 0; q < L::Q; ++q) {
-                const unsigned tx = (unsigned)(L::ex[q] > 0 ? xp : (L::ex[q] < 0 ? xm : t.x0));
-                const int ty = L::ey[q] > 0 ? yp : (L::ey[q] < 0 ? ym : t.y);
-                const int tz = L::ez[q] > 0 ? zp : (L::ez[q] < 0 ? zm : t.z);
-                const float *lq = a.lam_in + (size_t)q * g.stride;
-                float v = *at32(lq + (size_t)g.nx * (ty + g.ny * tz), tx);
-                // x + e_q solid <=> the pull of the opposite population at x bounces
-                if (MASK && q != 0 && ((lk[0] >> L::opp[q]) & 1u))
-                    v = *at32(a.lam_in + (size_t)L::opp[q] * g.stride, (unsigned)t.own);
-                gb[q] = v;
-            }
-        }
+        adjoint_pull<LAT, MASK>(g, t, a.lam_in, lk[0], gb);
         const float s = SOFT ? *at32(g.s, (unsigned)t.own) : 0.f;
         const Macro<LAT> m = macro<LAT>(p, d[0]);
         const float inv_cs = p.cs * p.inv_cs2;
@@ -606,22 +626,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_shift(AdjointArgs a)
     } else if (t.valid) {
         float d[1][L::Q], gb[L::Q];
         gather_tile<LAT, ST, MASK, 1>(g, static_cast<const T *>(a.state), p.inv_scale, t, lk, d);
-        {
-            const int xm = wrapm(t.x0, g.nx), xp = wrapp(t.x0, g.nx);
-            const int ym = wrapm(t.y, g.ny), yp = wrapp(t.y, g.ny);
-            const int zm = wrapm(t.z, g.nz), zp = wrapp(t.z, g.nz);
-#pragma unroll
-            for (int q = 0; q < L::Q; ++q) {
-                const unsigned tx = (unsigned)(L::ex[q] > 0 ? xp : (L::ex[q] < 0 ? xm : t.x0));
-                const int ty = L::ey[q] > 0 ? yp : (L::ey[q] < 0 ? ym : t.y);
-                const int tz = L::ez[q] > 0 ? zp : (L::ez[q] < 0 ? zm : t.z);
-                const float *lq = a.lam_in + (size_t)q * g.stride;
-                float v = *at32(lq + (size_t)g.nx * (ty + g.ny * tz), tx);
-                if (MASK && q != 0 && ((lk[0] >> L::opp[q]) & 1u))
-                    v = *at32(a.lam_in + (size_t)L::opp[q] * g.stride, (unsigned)t.own);
-                gb[q] = v;
-            }
-        }
+        adjoint_pull<LAT, MASK>(g, t, a.lam_in, lk[0], gb);
         const float s = SOFT ? *at32(g.s, (unsigned)t.own) : 0.f;
         const Macro<LAT> m = macro<LAT>(p, d[0]);
         const float om = p.omega;
@@ -719,14 +724,16 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_shift(AdjointArgs a)
         for (int c = 0; c < 4; ++c) part[c] = prev[c] + acc[c];
 }
 
-// Adjoint seed: lam(a, n) = e_a[axis] * value at fluid nodes (value = 1/(c_s norm)).
+// Adjoint seed: lam(a, n) = e_a[axis] * value at fluid nodes (value = 1/(c_s norm)), 0 at
+// obstacles and in free-slip wall planes.
 template <int LAT>
 __global__ __launch_bounds__(kBlock) void k_seed(Geometry g, float value, int axis, float *lam)
 {
     using L = Lat<LAT>;
     const Tile t = tile_of(g, (int)blockIdx.x);
     if (!t.valid) return;
-    const bool solid = g.mask && g.mask[t.own];
+    const bool solid = (g.mask && g.mask[t.own]) || ((g.slip & LBM_SLIP_Y) && (t.y == 0 || t.y == g.ny - 1)) ||
+                       ((g.slip & LBM_SLIP_Z) && (t.z == 0 || t.z == g.nz - 1));
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
         const int e = axis == 0 ? L::ex[q] : (axis == 1 ? L::ey[q] : L::ez[q]);

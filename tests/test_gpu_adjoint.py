@@ -179,23 +179,34 @@ def test_autograd_checkpointed_vs_oracle_fd():
     assert abs(ad - fd) <= TOL * abs(fd), (ad, fd)
 
 
-SHIFT_CASES = [
-    ("d3-soft-B", "D3V19", (20, 9, 7), 0.0, True, (1e-3, -4e-4, 2e-4), (2e-3, -1e-3, 3e-3), 0.75, 30, 7),
-    ("d2-walls-soft-B", "D2V9", (40, 9, 1), 0.15, True, (2e-3, -1e-3, 0.0), (0, 0, 4e-3), 0.8, 24, 5),
-    ("d2-walls", "D2V9", (33, 17, 1), 0.2, False, (1e-3, 5e-4, 0.0), (0, 0, 0), 0.6, 20, 6),
+SCHEME_CASES = [
+    # name, lattice, shape, obstacle fraction, soft, E, B, tau, T, K, forcing, slip
+    ("shift-d3-soft-B", "D3V19", (20, 9, 7), 0.0, True, (1e-3, -4e-4, 2e-4), (2e-3, -1e-3, 3e-3), 0.75, 30, 7,
+     "shift", 0),
+    ("shift-d2-walls-soft-B", "D2V9", (40, 9, 1), 0.15, True, (2e-3, -1e-3, 0.0), (0, 0, 4e-3), 0.8, 24, 5,
+     "shift", 0),
+    ("shift-d2-walls", "D2V9", (33, 17, 1), 0.2, False, (1e-3, 5e-4, 0.0), (0, 0, 0), 0.6, 20, 6, "shift", 0),
+    ("slip-d2-obst-soft-B", "D2V9", (40, 12, 1), 0.15, True, (2e-3, -1e-3, 0.0), (0, 0, 4e-3), 0.8, 24, 5,
+     "source", 1),
+    ("slip-yz-d3-shift-obst-soft-B", "D3V19", (16, 8, 7), 0.1, True, (1e-3, 3e-4, -2e-4), (2e-3, -1e-3, 3e-3),
+     0.7, 20, 6, "shift", 3),
+    ("slip-y-d3-source", "D3V19", (12, 9, 6), 0.0, False, (1e-3, 2e-4, 1e-4), (0, 0, 0), 0.65, 16, 5, "source", 1),
+    ("slip-z-d3-source-obst-B", "D3V19", (14, 6, 8), 0.12, False, (8e-4, -3e-4, 5e-4), (0, 3e-3, -2e-3), 0.7, 18, 4,
+     "source", 2),
 ]
 
 
-@pytest.mark.parametrize("case", SHIFT_CASES, ids=[c[0] for c in SHIFT_CASES])
-def test_shift_forcing_autograd_vs_oracle_fd(case):
-    """The velocity-shift adjoint (Sec. 9.3, Eq. 34; f^eq at u + tau (E + u x B)): the
-    checkpointed autograd gradient against FP64 central differences of the oracle's
-    forward step with the same forcing (the oracle has no adjoint of this scheme, so the
-    finite differences are the reference)."""
-    name, lat, shape, phi, soft, E0, B0, tau0, T, K = case
+@pytest.mark.parametrize("case", SCHEME_CASES, ids=[c[0] for c in SCHEME_CASES])
+def test_schemes_autograd_vs_oracle_fd(case):
+    """The adjoint of the velocity shift (Sec. 9.3, Eq. 34; f^eq at u + tau (E + u x B))
+    and of the free-slip wall planes (Sec. 9.4, specular reflection): the checkpointed
+    autograd gradient against FP64 central differences of the oracle's forward step with
+    the same scheme (the oracle has no adjoint of these, so the finite differences are the
+    reference)."""
+    name, lat, shape, phi, soft, E0, B0, tau0, T, K, forcing, slip = case
     wl = _wl((name, lat, shape, phi, soft, E0, B0, tau0), seed=33)
     pb = Problem(wl.lattice, wl.nx, wl.ny, wl.nz, T, wl.rho, wl.u, wl.mask, wl.B, checkpoint=K,
-                 forcing="shift")
+                 forcing=forcing, slip=slip)
     E = torch.tensor(wl.E, dtype=torch.float64, device="cuda", requires_grad=True)
     tau = torch.tensor(wl.tau, dtype=torch.float64, device="cuda", requires_grad=True)
     s = torch.tensor(wl.s, dtype=torch.float32, device="cuda", requires_grad=True) if soft else None
@@ -203,19 +214,25 @@ def test_shift_forcing_autograd_vs_oracle_fd(case):
     J.backward()
 
     def J_or(E_, tau_, s_):
-        m = OracleModel(wl.lattice, wl.nx, wl.ny, wl.nz, tau=tau_, E=E_, B=wl.B, forcing="shift")
+        m = OracleModel(wl.lattice, wl.nx, wl.ny, wl.nz, tau=tau_, E=E_, B=wl.B, forcing=forcing, slip=slip)
         return m.objective_current(m.run(m.init_state(wl.rho, wl.u, wl.mask), T, wl.mask, s_), 0, wl.mask)
 
     s64 = wl.s.astype(np.float32).astype(np.float64) if soft else None
     J0 = J_or(wl.E, wl.tau, s64)
     assert abs(J.item() - J0) <= 1e-5 * abs(J0)
+    fdE = []
     for i in range(wl.D):
         h = 1e-6
         Ep, Em = list(wl.E), list(wl.E)
         Ep[i] += h
         Em[i] -= h
-        fd = (J_or(Ep, wl.tau, s64) - J_or(Em, wl.tau, s64)) / (2 * h)
-        assert abs(E.grad[i].item() - fd) <= TOL * abs(fd), (i, E.grad[i].item(), fd)
+        fdE.append((J_or(Ep, wl.tau, s64) - J_or(Em, wl.tau, s64)) / (2 * h))
+    # a component that vanishes (no B, no obstacle or soft wall coupling the axes) is
+    # compared on the scale of the largest one: the kernel's FP32 per-node terms leave
+    # ~1e-9 of it there
+    big = max(abs(v) for v in fdE)
+    for i, fd in enumerate(fdE):
+        assert abs(E.grad[i].item() - fd) <= TOL * max(abs(fd), 1e-4 * big), (i, E.grad[i].item(), fd)
     h = 1e-5
     fd = (J_or(wl.E, wl.tau + h, s64) - J_or(wl.E, wl.tau - h, s64)) / (2 * h)
     assert abs(tau.grad.item() - fd) <= TOL * max(abs(fd), 1e-2 * abs(E.grad[0].item())), (tau.grad.item(), fd)

@@ -117,11 +117,3 @@ def test_slip_plug_flow_full_size(lattice, shape, slip):
     rho, u = gpu_fields(sim)
     fl = rho > 0
     assert np.ptp(u[0][fl]) < 1e-4 * np.abs(u[0][fl]).max()
-
-
-def test_adjoint_refuses_slip():
-    for forcing, slip in (("shift", lbm.SLIP_Y), ("source", lbm.SLIP_Y)):
-        sim = lbm.Simulation("D2V9", 16, 8, 1, tau=0.8, E=(1e-4, 0, 0), forcing=forcing, slip=slip)
-        sim.init(np.ones(16 * 8))
-        with pytest.raises(RuntimeError, match="adjoint"):
-            sim.adjoint_seed(0, 128)
