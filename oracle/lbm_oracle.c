@@ -370,8 +370,9 @@ void orc_totals(const orc_model *m, const uint8_t *mask, const double *fin, doub
  * grad_s is given, and grad[0..2] += dJ/dE, grad[3] += dJ/dtau.
  *
  * Per fluid node y:
- *   gbar_a = adjoint of g_a(y): lam_in at (y + e_a, a), or at (y, abar) when y + e_a
- *            is solid (transpose of the push with bounce-back);
+ *   gbar_a = adjoint of g_a(y): lam_in where orc_step writes g_a(y): at (y + e_a, a),
+ *            at the reflected destination and direction beside a free-slip plane, or at
+ *            (y, abar) when that destination is solid (transpose of the push);
  *   hbar_a = (1 - s) gbar_a                      (adjoint of f*_a);
  *   dJ/ds  = sum_a gbar_a (f_abar - f*_a);
  *   dJ/dtau = sum_a hbar_a (f_a - f^eq_a) / tau^2;
@@ -408,10 +409,19 @@ void orc_adjoint_step(const orc_model *m, const uint8_t *mask, const double *s,
                 const double sn = s ? s[n] : 0.0;
                 for (int a = 0; a < Q; ++a) {
                     f[a] = fin[a * N + n];
-                    const long d = node_index(m, wrap(x + m->e[a][0], m->nx),
-                                              wrap(y + m->e[a][1], m->ny),
-                                              wrap(z + m->e[a][2], m->nz));
-                    gbar[a] = (mask && mask[d]) ? lam_in[m->opp[a] * N + n] : lam_in[a * N + d];
+                    /* where orc_step sends g_a(x): slot b of d (reflected at a free-slip
+                     * plane), or slot opp(a) of x when d is solid */
+                    int tx = wrap(x + m->e[a][0], m->nx), ty = wrap(y + m->e[a][1], m->ny);
+                    int tz = wrap(z + m->e[a][2], m->nz), b = a;
+                    const int flip = (((m->slip & 1) && m->e[a][1] != 0 && (ty == 0 || ty == m->ny - 1)) ? 1 : 0) |
+                                     (((m->slip & 2) && m->e[a][2] != 0 && (tz == 0 || tz == m->nz - 1)) ? 2 : 0);
+                    if (flip) {
+                        if (flip & 1) ty = y;
+                        if (flip & 2) tz = z;
+                        b = reflected(m, a, flip);
+                    }
+                    const long d = node_index(m, tx, ty, tz);
+                    gbar[a] = (mask && mask[d]) ? lam_in[m->opp[a] * N + n] : lam_in[b * N + d];
                     hbar[a] = (1.0 - sn) * gbar[a];
                 }
                 orc_node_moments(m, f, &rho, u);

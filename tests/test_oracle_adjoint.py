@@ -12,26 +12,30 @@ from oracle.oracle import OracleModel
 from paper_1710_09472_amd import workloads as W
 
 
-def _J(lattice, shape, tau, E, B, f0, T, mask, s):
-    m = OracleModel(lattice, *shape, tau=tau, E=E, B=B)
+def _J(lattice, shape, tau, E, B, f0, T, mask, s, slip=0):
+    m = OracleModel(lattice, *shape, tau=tau, E=E, B=B, slip=slip)
     return m.objective_current(m.run(f0, T, mask, s), 0, mask)
 
 
 CASES = [
-    # lattice, shape, tau, E, B, solid fraction, soft s
-    ("D3V19", (6, 5, 4), 0.75, (1e-3, -4e-4, 2e-4), (0.0, 0.0, 0.0), 0.0, True),
-    ("D3V19", (5, 4, 4), 0.7, (1e-3, 3e-4, -2e-4), (2e-3, -1e-3, 3e-3), 0.15, True),
-    ("D2V9", (7, 6, 1), 0.8, (2e-3, -1e-3, 0.0), (0.0, 0.0, 4e-3), 0.2, True),
-    ("D2V9", (8, 5, 1), 0.6, (1e-3, 5e-4, 0.0), (0.0, 0.0, 0.0), 0.2, False),
+    # lattice, shape, tau, E, B, solid fraction, soft s, free-slip planes
+    ("D3V19", (6, 5, 4), 0.75, (1e-3, -4e-4, 2e-4), (0.0, 0.0, 0.0), 0.0, True, 0),
+    ("D3V19", (5, 4, 4), 0.7, (1e-3, 3e-4, -2e-4), (2e-3, -1e-3, 3e-3), 0.15, True, 0),
+    ("D2V9", (7, 6, 1), 0.8, (2e-3, -1e-3, 0.0), (0.0, 0.0, 4e-3), 0.2, True, 0),
+    ("D2V9", (8, 5, 1), 0.6, (1e-3, 5e-4, 0.0), (0.0, 0.0, 0.0), 0.2, False, 0),
+    # free-slip planes (Sec. 9.4): y in 2D; y and z in 3D with obstacles, B and soft s
+    ("D2V9", (7, 7, 1), 0.75, (2e-3, -1e-3, 0.0), (0.0, 0.0, 4e-3), 0.15, True, 1),
+    ("D3V19", (5, 6, 5), 0.7, (1e-3, 3e-4, -2e-4), (2e-3, -1e-3, 3e-3), 0.1, True, 3),
+    ("D3V19", (5, 4, 6), 0.8, (1e-3, 2e-4, 4e-4), (0.0, 2e-3, 0.0), 0.1, False, 2),
 ]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-{i}" for i, c in enumerate(CASES)])
 def test_gradient_vs_central_fd(case):
-    lattice, shape, tau, E, B, phi, soft = case
+    lattice, shape, tau, E, B, phi, soft, slip = case
     wl = W.random_fields(lattice, *shape, seed=11, solid_fraction=phi, soft=soft, umax=0.03)
     s = None if wl.s is None else 0.5 * wl.s
-    m = OracleModel(lattice, *shape, tau=tau, E=E, B=B)
+    m = OracleModel(lattice, *shape, tau=tau, E=E, B=B, slip=slip)
     f0 = m.init_state(wl.rho, wl.u, wl.mask)
     T = 6
     J, gs, g = m.gradient(f0, T, wl.mask, s)
@@ -41,11 +45,13 @@ def test_gradient_vs_central_fd(case):
         h = 1e-6
         Ep = list(E); Ep[i] += h
         Em = list(E); Em[i] -= h
-        fd = (_J(lattice, shape, tau, Ep, B, f0, T, wl.mask, s) - _J(lattice, shape, tau, Em, B, f0, T, wl.mask, s)) / (2 * h)
+        fd = (_J(lattice, shape, tau, Ep, B, f0, T, wl.mask, s, slip)
+              - _J(lattice, shape, tau, Em, B, f0, T, wl.mask, s, slip)) / (2 * h)
         assert abs(g[i] - fd) <= 1e-7 * max(abs(fd), 1e-3), (i, g[i], fd)
     # tau
     h = 1e-5
-    fd = (_J(lattice, shape, tau + h, E, B, f0, T, wl.mask, s) - _J(lattice, shape, tau - h, E, B, f0, T, wl.mask, s)) / (2 * h)
+    fd = (_J(lattice, shape, tau + h, E, B, f0, T, wl.mask, s, slip)
+          - _J(lattice, shape, tau - h, E, B, f0, T, wl.mask, s, slip)) / (2 * h)
     assert abs(g[3] - fd) <= 1e-7 * max(abs(fd), 1e-4), (g[3], fd)
     # s, directional
     if s is not None:
@@ -58,15 +64,18 @@ def test_gradient_vs_central_fd(case):
         assert abs(ad - fd) <= 1e-7 * abs(fd), (ad, fd)
 
 
-@pytest.mark.parametrize("lattice,shape", [("D2V9", (6, 5, 1)), ("D3V19", (4, 4, 3))])
-def test_adjoint_dot_product(lattice, shape):
-    """<lam, L v> = <L^T lam, v> for one linearised step L (FP64 central difference)."""
+@pytest.mark.parametrize("lattice,shape,slip", [("D2V9", (6, 5, 1), 0), ("D3V19", (4, 4, 3), 0),
+                                                ("D2V9", (6, 6, 1), 1), ("D3V19", (4, 5, 5), 3)])
+def test_adjoint_dot_product(lattice, shape, slip):
+    """<lam, L v> = <L^T lam, v> for one linearised step L (FP64 central difference);
+    with free-slip planes the transposed streaming includes the specular reflection."""
     wl = W.random_fields(lattice, *shape, seed=12, solid_fraction=0.2, soft=True, umax=0.03)
     m = OracleModel(lattice, *shape, tau=0.72, E=(1e-3, -1e-3, 5e-4 if lattice == "D3V19" else 0),
-                    B=(0, 0, 3e-3))
+                    B=(0, 0, 3e-3), slip=slip)
     F = m.init_state(wl.rho, wl.u, wl.mask)
     rng = np.random.default_rng(5)
-    fluid = np.tile(1 - (wl.mask if wl.mask is not None else 0), m.Q).astype(float)
+    solid = m._mask(wl.mask)
+    fluid = np.tile(1 - (solid if solid is not None else 0), m.Q).astype(float)
     v = rng.standard_normal(F.size) * 1e-2 * fluid
     lam = rng.standard_normal(F.size) * fluid
     h = 1e-4
