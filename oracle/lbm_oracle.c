@@ -381,6 +381,10 @@ void orc_totals(const orc_model *m, const uint8_t *mask, const double *fin, doub
  *   rhobar = sum_a hbar_a Phi_a / rho,  ubar_i = sum_a hbar_a dPhi_a/du_i,
  *     dPhi_a/du_i = rho w_a [ G_ai / tau + c2^2 xi_ai (xi_a . a_a) + (k1 xi_a^2 + k2) a_ai ];
  *   lam_out_b = (1 - 1/tau) hbar_b + s gbar_abar(b) + rhobar + ubar . (xi_b - u) / rho.
+ * Velocity shift (eq. u-update-force-term-eq): Phi_a = f^eq_a(rho, u') / tau with
+ * u' = u + tau (E + u x B) and no source; with Gs = sum_a hbar_a rho w_a G_a(u')
+ * (the adjoint of u'): rhobar = sum_a hbar_a f^eq_a / (tau rho), ubar = (Gs + tau B x Gs)
+ * / tau, dJ/dE = Gs, dJ/dtau = sum_a hbar_a (f_a - f^eq_a) / tau^2 + Gs . (E + u x B) / tau.
  * Solid nodes get lam_out = 0.
  */
 void orc_adjoint_step(const orc_model *m, const uint8_t *mask, const double *s,
@@ -425,6 +429,42 @@ void orc_adjoint_step(const orc_model *m, const uint8_t *mask, const double *s,
                     hbar[a] = (1.0 - sn) * gbar[a];
                 }
                 orc_node_moments(m, f, &rho, u);
+                if (m->forcing == 1) {
+                    /* velocity shift: Phi_a = f^eq_a(rho, u') / tau, u' = u + tau (E + u x B) */
+                    double ub[3], up[3], sh[3], Gs[3] = {0.0, 0.0, 0.0};
+                    cross3(u, m->B, ub);
+                    for (int i = 0; i < 3; ++i) {
+                        sh[i] = m->E[i] + ub[i];
+                        up[i] = u[i] + tau * sh[i];
+                    }
+                    if (m->D == 2) up[2] = sh[2] = 0.0;
+                    orc_equilibrium(m, rho, up, feq);
+                    for (int a = 0; a < Q; ++a) fs[a] = f[a] - (f[a] - feq[a]) / tau;
+                    double ds = 0.0, rhobar = 0.0;
+                    for (int a = 0; a < Q; ++a) {
+                        double G[3];
+                        grad_u_feq_unit(m, a, up, G); /* d f^eq_a / d u' = rho w_a G */
+                        ds += gbar[a] * (f[m->opp[a]] - fs[a]);
+                        gT += hbar[a] * ((f[a] - feq[a]) / (tau * tau) + rho * m->w[a] * dot3(G, sh) / tau);
+                        for (int i = 0; i < 3; ++i) Gs[i] += hbar[a] * rho * m->w[a] * G[i];
+                        rhobar += hbar[a] * feq[a] / (tau * rho);
+                    }
+                    gE0 += Gs[0];
+                    gE1 += Gs[1];
+                    gE2 += Gs[2];
+                    /* du'/du = 1 + tau [. x B]: ubar = (Gs + tau B x Gs) / tau */
+                    double bg[3], ubar[3];
+                    cross3(m->B, Gs, bg);
+                    for (int i = 0; i < 3; ++i) ubar[i] = (Gs[i] + tau * bg[i]) / tau;
+                    if (grad_s) grad_s[n] += ds;
+                    for (int b = 0; b < Q; ++b) {
+                        double uterm = 0.0;
+                        for (int i = 0; i < m->D; ++i) uterm += ubar[i] * (m->xi[b][i] - u[i]) / rho;
+                        lam_out[b * N + n] =
+                            (1.0 - 1.0 / tau) * hbar[b] + sn * gbar[m->opp[b]] + rhobar + uterm;
+                    }
+                    continue;
+                }
                 orc_equilibrium(m, rho, u, feq);
                 orc_source(m, rho, u, S);
                 for (int a = 0; a < Q; ++a) fs[a] = f[a] - (f[a] - feq[a]) / tau + S[a];

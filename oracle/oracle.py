@@ -214,10 +214,8 @@ class OracleModel:
 
     def adjoint_step(self, f_t, lam_in, mask=None, s=None, grad_s=None, grad=None):
         """One reverse step. Returns lam_out; accumulates into grad_s (N,) and
-        grad (4,) = (dJ/dEx, dJ/dEy, dJ/dEz, dJ/dtau) when given. Source forcing only;
+        grad (4,) = (dJ/dEx, dJ/dEy, dJ/dEz, dJ/dtau) when given. Both forcings,
         obstacles and free-slip planes (the transpose of the step's streaming)."""
-        if self.forcing != "source":
-            raise NotImplementedError("the oracle adjoint covers the source forcing")
         f_t = np.ascontiguousarray(f_t, dtype=np.float64)
         lam_in = np.ascontiguousarray(lam_in, dtype=np.float64)
         out = np.empty_like(lam_in)

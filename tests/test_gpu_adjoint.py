@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-4
 
 CASES = [
-    # name, lattice, shape, obstacle fraction, soft, E, B, tau, free-slip planes
+    # name, lattice, shape, obstacle fraction, soft, E, B, tau, free-slip planes[, forcing]
     ("d3-soft", "D3V19", (20, 9, 7), 0.0, True, (1e-3, -4e-4, 2e-4), (0, 0, 0), 0.75, 0),
     ("d3-all", "D3V19", (260, 5, 4), 0.12, True, (1e-3, 3e-4, -2e-4), (2e-3, -1e-3, 3e-3), 0.7, 0),
     ("d2-all", "D2V9", (300, 7, 1), 0.15, True, (2e-3, -1e-3, 0.0), (0, 0, 4e-3), 0.8, 0),
@@ -25,6 +25,11 @@ CASES = [
     ("d2-slip-all", "D2V9", (300, 9, 1), 0.15, True, (2e-3, -1e-3, 0.0), (0, 0, 4e-3), 0.8, 1),
     ("d3-slip-yz-all", "D3V19", (70, 7, 6), 0.1, True, (1e-3, 3e-4, -2e-4), (2e-3, -1e-3, 3e-3), 0.7, 3),
     ("d3-slip-z", "D3V19", (33, 5, 6), 0.0, False, (1e-3, 2e-4, 4e-4), (0, 2e-3, 0), 0.65, 2),
+    ("d3-shift-all", "D3V19", (260, 5, 4), 0.12, True, (1e-3, 3e-4, -2e-4), (2e-3, -1e-3, 3e-3), 0.7, 0, "shift"),
+    ("d2-shift-slip-all", "D2V9", (300, 9, 1), 0.15, True, (2e-3, -1e-3, 0.0), (0, 0, 4e-3), 0.8, 1, "shift"),
+    ("d3-shift-slip-yz", "D3V19", (70, 7, 6), 0.1, True, (1e-3, 3e-4, -2e-4), (2e-3, -1e-3, 3e-3), 0.7, 3,
+     "shift"),
+    ("d2-shift-walls", "D2V9", (33, 17, 1), 0.2, False, (1e-3, 5e-4, 0.0), (0, 0, 0), 0.6, 0, "shift"),
 ]
 
 
@@ -41,6 +46,7 @@ def _wl(case, seed=31):
 def test_adjoint_matches_oracle(case):
     wl = _wl(case)
     wl.slip = case[8]
+    wl.forcing = case[9] if len(case) > 9 else "source"
     T = 8
     sim = gpu_sim(wl)
     states = [sim.get_state()]
@@ -57,7 +63,8 @@ def test_adjoint_matches_oracle(case):
     torch.cuda.synchronize()
     lam0 = sim.adjoint_view(lam[cur]).double().cpu().numpy()
 
-    m = OracleModel(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E, B=wl.B, slip=wl.slip)
+    m = OracleModel(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E, B=wl.B, slip=wl.slip,
+                    forcing=wl.forcing)
     f0 = m.init_state(wl.rho, wl.u, wl.mask)
     J, gs_o, g_o = m.gradient(f0, T, wl.mask, wl.s)
     # oracle lam_0: rerun the reverse sweep keeping lam
@@ -207,9 +214,8 @@ SCHEME_CASES = [
 def test_schemes_autograd_vs_oracle_fd(case):
     """The adjoint of the velocity shift (Sec. 9.3, Eq. 34; f^eq at u + tau (E + u x B))
     and of the free-slip wall planes (Sec. 9.4, specular reflection): the checkpointed
-    autograd gradient against FP64 central differences of the oracle's forward step with
-    the same scheme (the oracle has no adjoint of these, so the finite differences are the
-    reference)."""
+    autograd gradient through the checkpointed reverse pass against FP64 central
+    differences of the oracle's forward step with the same scheme."""
     name, lat, shape, phi, soft, E0, B0, tau0, T, K, forcing, slip = case
     wl = _wl((name, lat, shape, phi, soft, E0, B0, tau0), seed=33)
     pb = Problem(wl.lattice, wl.nx, wl.ny, wl.nz, T, wl.rho, wl.u, wl.mask, wl.B, checkpoint=K,

@@ -12,8 +12,8 @@ from oracle.oracle import OracleModel
 from paper_1710_09472_amd import workloads as W
 
 
-def _J(lattice, shape, tau, E, B, f0, T, mask, s, slip=0):
-    m = OracleModel(lattice, *shape, tau=tau, E=E, B=B, slip=slip)
+def _J(lattice, shape, tau, E, B, f0, T, mask, s, slip=0, forcing="source"):
+    m = OracleModel(lattice, *shape, tau=tau, E=E, B=B, slip=slip, forcing=forcing)
     return m.objective_current(m.run(f0, T, mask, s), 0, mask)
 
 
@@ -27,15 +27,21 @@ CASES = [
     ("D2V9", (7, 7, 1), 0.75, (2e-3, -1e-3, 0.0), (0.0, 0.0, 4e-3), 0.15, True, 1),
     ("D3V19", (5, 6, 5), 0.7, (1e-3, 3e-4, -2e-4), (2e-3, -1e-3, 3e-3), 0.1, True, 3),
     ("D3V19", (5, 4, 6), 0.8, (1e-3, 2e-4, 4e-4), (0.0, 2e-3, 0.0), 0.1, False, 2),
+    # velocity shift (Sec. 9.3, Eq. 34): with obstacles, B and soft s; with slip planes
+    ("D3V19", (5, 4, 4), 0.7, (1e-3, 3e-4, -2e-4), (2e-3, -1e-3, 3e-3), 0.15, True, 0, "shift"),
+    ("D2V9", (7, 7, 1), 0.75, (2e-3, -1e-3, 0.0), (0.0, 0.0, 4e-3), 0.15, True, 1, "shift"),
+    ("D2V9", (8, 5, 1), 0.6, (1e-3, 5e-4, 0.0), (0.0, 0.0, 0.0), 0.2, False, 0, "shift"),
+    ("D3V19", (5, 6, 5), 0.8, (1e-3, 2e-4, 4e-4), (1e-3, 2e-3, -1e-3), 0.1, False, 3, "shift"),
 ]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-{i}" for i, c in enumerate(CASES)])
 def test_gradient_vs_central_fd(case):
-    lattice, shape, tau, E, B, phi, soft, slip = case
+    lattice, shape, tau, E, B, phi, soft, slip = case[:8]
+    forcing = case[8] if len(case) > 8 else "source"
     wl = W.random_fields(lattice, *shape, seed=11, solid_fraction=phi, soft=soft, umax=0.03)
     s = None if wl.s is None else 0.5 * wl.s
-    m = OracleModel(lattice, *shape, tau=tau, E=E, B=B, slip=slip)
+    m = OracleModel(lattice, *shape, tau=tau, E=E, B=B, slip=slip, forcing=forcing)
     f0 = m.init_state(wl.rho, wl.u, wl.mask)
     T = 6
     J, gs, g = m.gradient(f0, T, wl.mask, s)
@@ -45,13 +51,13 @@ def test_gradient_vs_central_fd(case):
         h = 1e-6
         Ep = list(E); Ep[i] += h
         Em = list(E); Em[i] -= h
-        fd = (_J(lattice, shape, tau, Ep, B, f0, T, wl.mask, s, slip)
-              - _J(lattice, shape, tau, Em, B, f0, T, wl.mask, s, slip)) / (2 * h)
+        fd = (_J(lattice, shape, tau, Ep, B, f0, T, wl.mask, s, slip, forcing)
+              - _J(lattice, shape, tau, Em, B, f0, T, wl.mask, s, slip, forcing)) / (2 * h)
         assert abs(g[i] - fd) <= 1e-7 * max(abs(fd), 1e-3), (i, g[i], fd)
     # tau
     h = 1e-5
-    fd = (_J(lattice, shape, tau + h, E, B, f0, T, wl.mask, s, slip)
-          - _J(lattice, shape, tau - h, E, B, f0, T, wl.mask, s, slip)) / (2 * h)
+    fd = (_J(lattice, shape, tau + h, E, B, f0, T, wl.mask, s, slip, forcing)
+          - _J(lattice, shape, tau - h, E, B, f0, T, wl.mask, s, slip, forcing)) / (2 * h)
     assert abs(g[3] - fd) <= 1e-7 * max(abs(fd), 1e-4), (g[3], fd)
     # s, directional
     if s is not None:
@@ -64,14 +70,16 @@ def test_gradient_vs_central_fd(case):
         assert abs(ad - fd) <= 1e-7 * abs(fd), (ad, fd)
 
 
-@pytest.mark.parametrize("lattice,shape,slip", [("D2V9", (6, 5, 1), 0), ("D3V19", (4, 4, 3), 0),
-                                                ("D2V9", (6, 6, 1), 1), ("D3V19", (4, 5, 5), 3)])
-def test_adjoint_dot_product(lattice, shape, slip):
+@pytest.mark.parametrize("lattice,shape,slip,forcing", [
+    ("D2V9", (6, 5, 1), 0, "source"), ("D3V19", (4, 4, 3), 0, "source"),
+    ("D2V9", (6, 6, 1), 1, "source"), ("D3V19", (4, 5, 5), 3, "source"),
+    ("D2V9", (6, 5, 1), 0, "shift"), ("D3V19", (4, 5, 5), 3, "shift")])
+def test_adjoint_dot_product(lattice, shape, slip, forcing):
     """<lam, L v> = <L^T lam, v> for one linearised step L (FP64 central difference);
     with free-slip planes the transposed streaming includes the specular reflection."""
     wl = W.random_fields(lattice, *shape, seed=12, solid_fraction=0.2, soft=True, umax=0.03)
     m = OracleModel(lattice, *shape, tau=0.72, E=(1e-3, -1e-3, 5e-4 if lattice == "D3V19" else 0),
-                    B=(0, 0, 3e-3), slip=slip)
+                    B=(0, 0, 3e-3) if lattice == "D2V9" else (1e-3, -2e-3, 3e-3), slip=slip, forcing=forcing)
     F = m.init_state(wl.rho, wl.u, wl.mask)
     rng = np.random.default_rng(5)
     solid = m._mask(wl.mask)
