@@ -402,7 +402,10 @@ __device__ __forceinline__ void adjoint_pull(const Geometry &g, const Tile &t, c
             constexpr int pyz = reflected<LAT>(q, true, true);
             p = fy ? (fz ? pyz : py) : (fz ? pz : q);
         }
-        float v = *at32(lam_in + (size_t)p * g.stride + (size_t)g.nx * (ty + g.ny * tz), tx);
+        const float *src = at32(lam_in + (size_t)p * g.stride + (size_t)g.nx * (ty + g.ny * tz), tx);
+        // as in the forward pull: values of the node's own column are read once (streamed);
+        // x-shifted ones share cache lines with the neighbouring lanes
+        float v = L::ex[q] == 0 ? __builtin_nontemporal_load(src) : *src;
         if constexpr (MASK && q != 0)
             if ((lk >> L::opp[q]) & 1u) v = *at32(lam_in + (size_t)L::opp[q] * g.stride, (unsigned)t.own);
         gb[q] = v;
@@ -563,7 +566,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
             constexpr int q = decltype(qc)::value;
             float out = __builtin_fmaf(one_om, one_s * gb[q], base + edot<LAT, q>(Vs));
             if (SOFT) out = __builtin_fmaf(s, gb[L::opp[q]], out);
-            *at32(a.lam_out + (size_t)q * g.stride, (unsigned)t.own) = out;
+            __builtin_nontemporal_store(out, at32(a.lam_out + (size_t)q * g.stride, (unsigned)t.own));
         });
         if (SOFT && a.grad_s) *at32(a.grad_s, (unsigned)t.own) = gs_prev + ds;
         acc[0] = (double)m.rho * (double)dE[0];
@@ -706,7 +709,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_shift(AdjointArgs a)
             constexpr int q = decltype(qc)::value;
             float out = __builtin_fmaf(one_om, one_s * gb[q], base + edot<LAT, q>(H));
             if (SOFT) out = __builtin_fmaf(s, gb[L::opp[q]], out);
-            *at32(a.lam_out + (size_t)q * g.stride, (unsigned)t.own) = out;
+            __builtin_nontemporal_store(out, at32(a.lam_out + (size_t)q * g.stride, (unsigned)t.own));
         });
         if (SOFT && a.grad_s) *at32(a.grad_s, (unsigned)t.own) = gs_prev + ds;
         const float rtc = m.rho * tau * p.cs;
