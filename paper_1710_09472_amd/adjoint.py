@@ -39,6 +39,7 @@ class Problem:
     axis: int = 0
     forcing: str = "source"         # "source" (Eq. 31) or "shift" (Sec. 9.3)
     slip: int = 0                   # free-slip wall planes (Sec. 9.4): bit 0 y, bit 1 z
+    inplace: bool = False           # one state buffer (checkpoints still in two-buffer layout)
 
     @property
     def N(self):
@@ -47,7 +48,7 @@ class Problem:
 
 def _make_sim(pb: Problem, E, tau, s):
     return Simulation(pb.lattice, pb.nx, pb.ny, pb.nz, tau=float(tau), E=[float(v) for v in E], B=pb.B,
-                      mask=pb.mask, s=s, forcing=pb.forcing, slip=pb.slip)
+                      mask=pb.mask, s=s, forcing=pb.forcing, slip=pb.slip, inplace=pb.inplace)
 
 
 def forward_with_checkpoints(pb: Problem, E, tau, s):

@@ -143,6 +143,26 @@ def test_adjoint_of_16bit_state_vs_oracle_at_decoded_states(storage, k, name):
         assert err_s < TOL, err_s
 
 
+def test_inplace_handle_gives_the_same_gradients():
+    """An in-place (one state buffer) handle: its checkpoints come from lbm_get_state, which
+    rearranges the odd-parity layout, so with odd segment lengths (T = 13, K = 5) the
+    gradients equal the two-buffer handle's bit for bit (the in-place step is bitwise the
+    two-buffer step)."""
+    wl = _wl(CASES[5], seed=34)  # 3D, obstacles, soft s, B, y+z slip planes
+    out = []
+    for inplace in (False, True):
+        pb = Problem(wl.lattice, wl.nx, wl.ny, wl.nz, 13, wl.rho, wl.u, wl.mask, wl.B, checkpoint=5,
+                     slip=CASES[5][8], inplace=inplace)
+        E = torch.tensor(wl.E, dtype=torch.float64, device="cuda", requires_grad=True)
+        tau = torch.tensor(wl.tau, dtype=torch.float64, device="cuda", requires_grad=True)
+        s = torch.tensor(wl.s, dtype=torch.float32, device="cuda", requires_grad=True)
+        J = mean_current(E, tau, s, pb)
+        J.backward()
+        out.append((J.detach().cpu(), E.grad.cpu(), tau.grad.cpu(), s.grad.cpu()))
+    for a, b in zip(*out):
+        assert torch.equal(a, b), (a, b)
+
+
 def test_held_partials_match_per_step_reduction():
     """dJ/dE, dJ/dtau held as per-block partials over the reverse pass (grad_scalars
     passed on the last step only) equal the per-step reductions up to the order of the
