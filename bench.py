@@ -79,6 +79,11 @@ def make_workload(name: str):
             "poiseuille_paper_2d": W.poiseuille_paper_2d}[name]()
 
 
+def wl_q(wl) -> int:
+    """Populations per node of a workload's lattice."""
+    return {"D2V9": 9, "D3V19": 19, "D1V7": 7}[wl.lattice]
+
+
 def bytes_per_node(Q: int, elem: int) -> int:
     """Algorithmic HBM bytes of one node update: Q populations read and Q written."""
     return 2 * Q * elem
@@ -424,9 +429,13 @@ def main():
         extras["adjoint"] = {}
         for key, forcing in (("step_only_4096sq", "source"), ("step_only_4096sq_shift", "shift")):
             t_adj, t_fwd = adjoint_ratio(wl, max(20, args.steps // 4), 5, forcing)
+            # algorithmic bytes of one adjoint node update (FP32 state, no walls, no soft
+            # porosity): read the state's Q values, read lambda(t+1), write lambda(t)
+            gbs = 3 * wl_q(wl) * 4 * wl.N / t_adj / 1e9
             extras["adjoint"][key] = {"ms_per_step": round(t_adj * 1e3, 5),
                                       "forward_ms_per_step": round(t_fwd * 1e3, 5),
-                                      "ratio_to_forward": round(t_adj / t_fwd, 3)}
+                                      "ratio_to_forward": round(t_adj / t_fwd, 3),
+                                      "achieved_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
         extras["adjoint"]["checkpointed_128cube"] = adjoint_pipeline()
         extras["inplace"] = {"f32": inplace_extra(wl, "f32", 0, args.steps, args.warmup),
                              "f16": inplace_extra(wl, "f16", F16_SCALE["throughput_2d"], args.steps, args.warmup)}
