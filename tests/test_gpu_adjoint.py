@@ -163,6 +163,38 @@ def test_inplace_handle_gives_the_same_gradients():
         assert torch.equal(a, b), (a, b)
 
 
+@pytest.mark.parametrize("forcing", ["source", "shift"])
+def test_adjoint_step_full_size_sampled_rows(forcing):
+    """The adjoint step at 4096^2 in the configuration the benchmark times (tau 0.6,
+    E = (1e-6, 0, 0), no walls), from the state after 20 steps with a seeded random
+    lambda(t+1). lambda(t) at a node needs only f at the node and lambda(t+1) at its
+    neighbours, so the oracle recomputes sampled rows y exactly on the three-row window
+    (y - 1, y, y + 1) of full width (x stays periodic); the middle row is compared."""
+    wl = W.throughput_2d()
+    nx, ny = wl.nx, wl.ny
+    E = (1e-6, 0.0, 0.0)
+    sim = lbm.Simulation("D2V9", nx, ny, 1, tau=wl.tau, E=E, forcing=forcing)
+    sim.init(wl.rho)
+    sim.step(20)
+    state = sim.get_state()
+    gen = torch.Generator().manual_seed(7)
+    lam_in = torch.randn(sim.new_adjoint().numel(), generator=gen).to("cuda")
+    lam_out = sim.new_adjoint()
+    gsc = torch.zeros(4, dtype=torch.float64, device="cuda")
+    sim.adjoint_step(state, lam_in, lam_out, None, gsc)
+    torch.cuda.synchronize()
+    m = OracleModel("D2V9", nx, 3, 1, tau=wl.tau, E=E, forcing=forcing)
+    perm = permutation_to_oracle(sim, m)
+    f = sim.export_f64(state).cpu().numpy()[perm].reshape(m.Q, ny, nx)
+    li = sim.adjoint_view(lam_in).double().cpu().numpy()[perm].reshape(m.Q, ny, nx)
+    lo_gpu = sim.adjoint_view(lam_out).double().cpu().numpy()[perm].reshape(m.Q, ny, nx)
+    for y in (0, 1, 2047, ny - 1):
+        rows = [(y - 1) % ny, y, (y + 1) % ny]
+        out = m.adjoint_step(f[:, rows, :].reshape(-1), li[:, rows, :].reshape(-1)).reshape(m.Q, 3, nx)[:, 1, :]
+        err = np.abs(lo_gpu[:, y, :] - out).max() / np.abs(out).max()
+        assert err < TOL, (y, err)
+
+
 def test_held_partials_match_per_step_reduction():
     """dJ/dE, dJ/dtau held as per-block partials over the reverse pass (grad_scalars
     passed on the last step only) equal the per-step reductions up to the order of the
