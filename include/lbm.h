@@ -241,7 +241,8 @@ int lbm_set_tau(lbm_t h, double tau);
 int lbm_adjoint_seed(lbm_t h, int axis, double norm, float *lam);
 
 /* One reverse step of the discrete adjoint of lbm_step (not in the paper), for either
- * forcing (the source of Eq. 31, or the velocity shift of Sec. 9.3, Eq. 34), bounce-back
+ * forcing (the source term of Sec. 7, or the velocity shift of eq. (u-update-force-term-eq)
+ * used in Sec. 9.3), bounce-back
  * obstacles, partial bounce-back and the free-slip wall planes of Sec. 9.4:
  * LBM_EUNSUPPORTED for the D1V7 thermal model (as lbm_adjoint_seed).
  *   state   : the state buffer whose populations are pre-collision at step t (what the

@@ -37,7 +37,7 @@ class Problem:
     B: tuple = (0.0, 0.0, 0.0)
     checkpoint: int = 50
     axis: int = 0
-    forcing: str = "source"         # "source" (Eq. 31) or "shift" (Sec. 9.3)
+    forcing: str = "source"         # "source" (Sec. 7) or "shift" (eq. (u-update-force-term-eq))
     slip: int = 0                   # free-slip wall planes (Sec. 9.4): bit 0 y, bit 1 z
     inplace: bool = False           # one state buffer (checkpoints still in two-buffer layout)
 

@@ -316,9 +316,9 @@ SCHEME_CASES = [
 
 @pytest.mark.parametrize("case", SCHEME_CASES, ids=[c[0] for c in SCHEME_CASES])
 def test_schemes_autograd_vs_oracle_fd(case):
-    """The adjoint of the velocity shift (Sec. 9.3, Eq. 34; f^eq at u + tau (E + u x B))
-    and of the free-slip wall planes (Sec. 9.4, specular reflection): the checkpointed
-    autograd gradient through the checkpointed reverse pass against FP64 central
+    """The adjoint of the velocity shift (eq. (u-update-force-term-eq), Sec. 9.3; f^eq at
+    u + tau (E + u x B)) and of the free-slip wall planes (Sec. 9.4, specular reflection):
+    the autograd gradient through the checkpointed reverse pass against FP64 central
     differences of the oracle's forward step with the same scheme."""
     name, lat, shape, phi, soft, E0, B0, tau0, T, K, forcing, slip = case
     wl = _wl((name, lat, shape, phi, soft, E0, B0, tau0), seed=33)

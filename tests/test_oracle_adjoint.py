@@ -27,7 +27,7 @@ CASES = [
     ("D2V9", (7, 7, 1), 0.75, (2e-3, -1e-3, 0.0), (0.0, 0.0, 4e-3), 0.15, True, 1),
     ("D3V19", (5, 6, 5), 0.7, (1e-3, 3e-4, -2e-4), (2e-3, -1e-3, 3e-3), 0.1, True, 3),
     ("D3V19", (5, 4, 6), 0.8, (1e-3, 2e-4, 4e-4), (0.0, 2e-3, 0.0), 0.1, False, 2),
-    # velocity shift (Sec. 9.3, Eq. 34): with obstacles, B and soft s; with slip planes
+    # velocity shift (eq. (u-update-force-term-eq), Sec. 9.3): with obstacles, B and soft s; with slip planes
     ("D3V19", (5, 4, 4), 0.7, (1e-3, 3e-4, -2e-4), (2e-3, -1e-3, 3e-3), 0.15, True, 0, "shift"),
     ("D2V9", (7, 7, 1), 0.75, (2e-3, -1e-3, 0.0), (0.0, 0.0, 4e-3), 0.15, True, 1, "shift"),
     ("D2V9", (8, 5, 1), 0.6, (1e-3, 5e-4, 0.0), (0.0, 0.0, 0.0), 0.2, False, 0, "shift"),
