@@ -403,8 +403,9 @@ __device__ __forceinline__ void adjoint_pull(const Geometry &g, const Tile &t, c
             p = fy ? (fz ? pyz : py) : (fz ? pz : q);
         }
         const float *src = at32(lam_in + (size_t)p * g.stride + (size_t)g.nx * (ty + g.ny * tz), tx);
-        // as in the forward pull: values of the node's own column are read once (streamed);
-        // x-shifted ones share cache lines with the neighbouring lanes
+        // as in the forward pull: unshifted in x, a wave's loads cover whole cache lines that
+        // no other wave reads (streamed loads); x-shifted loads reach one element into the
+        // neighbouring wave's lines, which the cache then serves
         float v = L::ex[q] == 0 ? __builtin_nontemporal_load(src) : *src;
         if constexpr (MASK && q != 0)
             if ((lk >> L::opp[q]) & 1u) v = *at32(lam_in + (size_t)L::opp[q] * g.stride, (unsigned)t.own);
