@@ -47,7 +47,12 @@ def test_adjoint_matches_oracle(case):
     wl = _wl(case)
     wl.slip = case[8]
     wl.forcing = case[9] if len(case) > 9 else "source"
-    T = 8
+    _check_against_oracle(wl, 8)
+
+
+def _check_against_oracle(wl, T):
+    """T forward steps on the GPU, then the T reverse steps from the seed of the mean
+    x-current; lambda(0), dJ/dE, dJ/dtau and dJ/ds against the oracle's adjoint."""
     sim = gpu_sim(wl)
     states = [sim.get_state()]
     for _ in range(T):
@@ -89,6 +94,22 @@ def test_adjoint_matches_oracle(case):
         gsv = gs.double().cpu().numpy()
         err_s = np.abs(gsv - gs_o).max() / np.abs(gs_o).max()
         assert err_s < TOL, err_s
+
+
+
+TINY = [  # grids of one or a few nodes: every neighbour wraps onto the node or its row
+    ("D2V9", (1, 1, 1), "source"), ("D2V9", (2, 3, 1), "shift"), ("D3V19", (1, 1, 1), "shift"),
+    ("D3V19", (3, 1, 2), "source"),
+]
+
+
+@pytest.mark.parametrize("lattice,shape,forcing", TINY, ids=[f"{c[0]}-{'x'.join(map(str, c[1]))}-{c[2]}" for c in TINY])
+def test_adjoint_tiny_grids(lattice, shape, forcing):
+    wl = W.random_fields(lattice, *shape, seed=35, solid_fraction=0.0, soft=True, umax=0.03)
+    wl.E = (1e-3, -4e-4, 2e-4 if lattice == "D3V19" else 0.0)
+    wl.B = (0.0, 0.0, 3e-3) if lattice == "D2V9" else (1e-3, -2e-3, 3e-3)
+    wl.tau, wl.s, wl.forcing = 0.7, 0.5 * wl.s, forcing
+    _check_against_oracle(wl, 5)
 
 
 STORAGE_CASES = [("f16", 12, "d2-all"), ("bf16", 0, "d3-all"), ("f16", 12, "d3-shift-slip-yz")]
