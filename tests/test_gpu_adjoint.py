@@ -50,15 +50,15 @@ def test_adjoint_matches_oracle(case):
     _check_against_oracle(wl, 8)
 
 
-def _check_against_oracle(wl, T):
+def _check_against_oracle(wl, T, axis=0):
     """T forward steps on the GPU, then the T reverse steps from the seed of the mean
-    x-current; lambda(0), dJ/dE, dJ/dtau and dJ/ds against the oracle's adjoint."""
+    current along `axis`; lambda(0), dJ/dE, dJ/dtau and dJ/ds against the oracle's adjoint."""
     sim = gpu_sim(wl)
     states = [sim.get_state()]
     for _ in range(T):
         sim.step(1)
         states.append(sim.get_state())
-    lam = [sim.adjoint_seed(0, wl.N), sim.new_adjoint()]
+    lam = [sim.adjoint_seed(axis, wl.N), sim.new_adjoint()]
     gs = torch.zeros(wl.N, dtype=torch.float32, device="cuda")
     gsc = torch.zeros(4, dtype=torch.float64, device="cuda")
     cur = 0
@@ -71,12 +71,12 @@ def _check_against_oracle(wl, T):
     m = OracleModel(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E, B=wl.B, slip=wl.slip,
                     forcing=wl.forcing)
     f0 = m.init_state(wl.rho, wl.u, wl.mask)
-    J, gs_o, g_o = m.gradient(f0, T, wl.mask, wl.s)
+    J, gs_o, g_o = m.gradient(f0, T, wl.mask, wl.s, axis=axis)
     # oracle lam_0: rerun the reverse sweep keeping lam
     st = [f0]
     for _ in range(T):
         st.append(m.step(st[-1], wl.mask, wl.s))
-    lo = m.seed_current(0, mask=wl.mask)
+    lo = m.seed_current(axis, mask=wl.mask)
     for t in range(T - 1, -1, -1):
         lo = m.adjoint_step(st[t], lo, wl.mask, wl.s)
     lo = lo.reshape(m.Q, m.N)
@@ -95,6 +95,16 @@ def _check_against_oracle(wl, T):
         err_s = np.abs(gsv - gs_o).max() / np.abs(gs_o).max()
         assert err_s < TOL, err_s
 
+
+
+@pytest.mark.parametrize("name,axis", [("d2-all", 1), ("d3-all", 1), ("d3-shift-slip-yz", 2)])
+def test_adjoint_of_the_other_currents(name, axis):
+    """J = mean y- or z-current: the seed's other axes, against the oracle's adjoint."""
+    case = next(c for c in CASES if c[0] == name)
+    wl = _wl(case)
+    wl.slip = case[8]
+    wl.forcing = case[9] if len(case) > 9 else "source"
+    _check_against_oracle(wl, 8, axis)
 
 
 TINY = [  # grids of one or a few nodes: every neighbour wraps onto the node or its row
