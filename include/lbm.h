@@ -17,7 +17,7 @@
  *     rho E to rho u per step and B rotates u by |B| radians per step. In 2D only
  *     E_x, E_y and B_z may be non-zero.
  *   - Every device pointer is borrowed: the library owns no device memory. The caller
- *     allocates state and work buffers of the sizes lbm_buffer_sizes reports and keeps
+ *     allocates state and work buffers of the sizes lbm_workspace_bytes reports and keeps
  *     them (and the mask and s arrays) alive while the handle exists.
  *   - All device work is enqueued on the HIP stream given to lbm_create; only
  *     lbm_current synchronises. A handle is not thread-safe.
@@ -122,20 +122,32 @@ typedef struct {
  * weight comes out <= 0 (D3V15 under the electron weight). */
 int lbm_compute_constants(const lbm_params *p, lbm_constants *out);
 
-/* Host only. Q, D and the library's lattice vectors e (Q x 3 ints, row a = e_a)
- * in the order used by every Q-indexed buffer of this library. e may be NULL. */
+/* Host only. Q, D and the library's lattice vectors e (Q x 3 ints, row a = e_a) of the
+ * quadratures of Sec. 8, Table 1 and App. A, in the order used by every Q-indexed buffer
+ * of this library. e may be NULL. LBM_EINVAL for an unknown lattice and for D3V15. */
 int lbm_lattice_info(int lattice, int *Q, int *D, int *e);
 
-/* Host only. Sizes of the device buffers a handle with parameters *p needs:
+/* Host only; not in the paper (buffer sizing of this library). Sizes of the device
+ * buffers a handle with parameters *p needs, so that the caller can allocate them (the
+ * library owns no device memory):
  *   state_bytes : one population state (Q arrays of `stride` elements, storage type)
- *   work_bytes  : scratch for reductions (8-byte aligned)
+ *   work_bytes  : scratch for reductions, link masks and held adjoint partials
+ *                 (8-byte aligned; any initial content)
+ * Same validation and errors as lbm_create (LBM_EINVAL, e.g. Q * N >= 2^31). Either
+ * output pointer may be NULL. */
+int lbm_workspace_bytes(const lbm_params *p, size_t *state_bytes, size_t *work_bytes);
+
+/* Host only; not in the paper. lbm_workspace_bytes plus the sizes the adjoint and the
+ * caller's own indexing need:
  *   adjoint_bytes : one adjoint field (Q x stride floats)
  *   stride      : elements between population arrays (>= nx*ny*nz)
  * Any output pointer may be NULL. */
 int lbm_buffer_sizes(const lbm_params *p, size_t *state_bytes, size_t *work_bytes,
                      size_t *adjoint_bytes, size_t *stride);
 
-/* Validate *p, compute the constants and bind the buffers.
+/* Validate *p, compute the constants and bind the buffers: the problem statement of the
+ * electron model of Sec. 9.1 (lattice and weight, relaxation time tau, fields E and B,
+ * solids), with the constants of Sec. 3 and the quadrature weights of Sec. 8 / Table 1.
  *   mask    : device uint8[N], 1 = solid, or NULL (no solids)
  *   s       : device float[N] in [0, 1], partial bounce-back fraction (Walsh et al.
  *             2009 gray lattice, not in the paper), or NULL
@@ -157,9 +169,13 @@ int lbm_buffer_sizes(const lbm_params *p, size_t *state_bytes, size_t *work_byte
 int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *state_a,
                void *state_b, void *work, void *stream, lbm_t *out);
 
-/* Initial state f_a(x) = f^eq_a(rho(x), u(x)) (reduced EDF, Sec. 9.1), no force
- * correction. rho: device double[N]; u: device double[D*N] SoA (u_x block, then u_y,
- * ...), xi-units, or NULL for u = 0. Values at solid nodes are ignored. Async. */
+/* Initial state f_a(x) = f^eq_a(rho(x), u(x)) (reduced EDF,
+ * eq. (feq-reduced-applied-electrons-in-metals-eq), Sec. 9.1), no force correction, as
+ * the runs of Sec. 9.2-9.4 start from an equilibrium. rho: device double[N]; u: device
+ * double[D*N] SoA (u_x block, then u_y, ...), xi-units, or NULL for u = 0. The fields are
+ * FP64 (not float) so that a density given to more digits than FP32 holds, e.g.
+ * rho(mu) from lbm_density_from_mu, is rounded once, inside the kernel, to the deviation
+ * it stores. Values at solid nodes are ignored. Async. */
 int lbm_init(lbm_t h, const double *rho, const double *u);
 
 /* Initial state of the fourth-order thermal model (LBM_D1V7 only, LBM_EUNSUPPORTED
@@ -184,13 +200,15 @@ int lbm_init_thermal(lbm_t h, const double *rho, const double *u, const double *
  * between the two in-place kernels. Async. */
 int lbm_step(lbm_t h, int nsteps);
 
-/* One step from the state in `src` into `dst` (device state buffers of state_bytes,
+/* One step of the discrete BGK update of Sec. 9.1 (as lbm_step) from the state in `src`
+ * into `dst` (device state buffers of state_bytes,
  * distinct, neither need be the handle's own; two-buffer layout, as lbm_get_state
  * writes it); the handle's state is not touched. Used to recompute trajectories for
  * the adjoint. Async. */
 int lbm_step_from(lbm_t h, const void *src, void *dst);
 
-/* Fields of the current state (pre-collision): rho (device float[N]) and u (device
+/* Macroscopic fields of eq. (mac-fields-model-sec-eq), Sec. 9.1, of the current state
+ * (pre-collision): rho = sum_a f_a (device float[N]) and u = sum_a f_a xi_a / rho (device
  * float[D*N] SoA, xi-units). Solid nodes get 0. Either pointer may be NULL. Async. */
 int lbm_moments(lbm_t h, float *rho, float *u);
 
@@ -199,11 +217,14 @@ int lbm_moments(lbm_t h, float *rho, float *u);
 int lbm_thetabar(lbm_t h, float *thetabar);
 
 /* Thermal model (LBM_D1V7) only: sum over nodes of sum_a f_a xi_a^2 (twice the kinetic
- * energy, conserved by the collision), FP64 into host *out. Synchronises the stream. */
+ * energy, the second moment the energy equation of Sec. 6 conserves, eq. energy-cons-eq),
+ * FP64 into host *out. Synchronises the stream. */
 int lbm_energy(lbm_t h, double *out);
 
-/* Totals over fluid nodes of the current state, accumulated in FP64:
- * out[0] = sum rho, out[1..3] = sum rho u (xi-units; out[3] = 0 in 2D). out is host
+/* Totals over fluid nodes of the current state, accumulated in FP64: the mass and the
+ * current of Sec. 9.4 (Ohm's law: the current through the sample is rho times the mean
+ * velocity over its cross-section), out[0] = sum rho, out[1..3] = sum rho u (xi-units;
+ * out[3] = 0 in 2D), with rho and u of eq. (mac-fields-model-sec-eq). out is host
  * memory. Synchronises the stream. LBM_ENONFINITE if any total is NaN/Inf. */
 int lbm_current(lbm_t h, double out[4]);
 
@@ -216,24 +237,32 @@ int lbm_current(lbm_t h, double out[4]);
  * Synchronises the stream; LBM_ENONFINITE if the average is NaN/Inf. */
 int lbm_speed_change(lbm_t h, const float *u, float *speed, int have_previous, double *out);
 
-/* Copy the current state to / from a caller device buffer of state_bytes (the
- * library's opaque two-buffer layout: post-collision populations of the previous step).
+/* Not in the paper (state I/O for checkpointing and restarts). Copy the current state
+ * to / from a caller device buffer of state_bytes (the library's opaque two-buffer
+ * layout: post-collision populations of the previous step).
  * With one state buffer after an odd number of steps, lbm_get_state rearranges the
  * in-place layout into dst with a kernel (dst must not be state_a, LBM_EINVAL);
  * lbm_set_state restarts the in-place sequence from the two-buffer layout. Async. */
 int lbm_get_state(lbm_t h, void *dst);
 int lbm_set_state(lbm_t h, const void *src);
 
-/* Pre-collision populations f_a (full values, not deviations) of a state in FP64:
+/* Not in the paper (state I/O, for checking). Pre-collision populations f_a (full
+ * values, not deviations) of a state in FP64:
  * dst is device double[Q*N], f_a of node n at dst[a*N + n] in lbm_lattice_info order.
  * state = NULL means the current state. Solid nodes get 0. Async. */
 int lbm_export_f64(lbm_t h, const void *state, double *dst);
 
-/* Change E, B or tau of an existing handle (same validation as lbm_create). */
+/* Change the fields of the Lorentz acceleration a = E + xi x B of Sec. 7 on an existing
+ * handle (same validation as lbm_create), e.g. for the field sweep of Sec. 9.4. */
 int lbm_set_fields(lbm_t h, const double E[3], const double B[3]);
+
+/* Change the relaxation time tau of the discrete BGK update of Sec. 9.1 on an existing
+ * handle (tau > 1/2, LBM_EINVAL otherwise), e.g. for the tau sweep of Sec. 9.3. */
 int lbm_set_tau(lbm_t h, double tau);
 
-/* Adjoint seed for J = (1/norm) sum over fluid nodes x and a of f_a(x, T) xi_a[axis]:
+/* Not in the paper (the adjoint is a growth of the method). Adjoint seed for the mean
+ * current of Sec. 9.4 as the objective, J = (1/norm) sum over fluid nodes x and a of
+ * f_a(x, T) xi_a[axis]:
  * lam[a*stride + n] = xi_a[axis]/norm at fluid nodes, 0 at solids (obstacles and free-slip
  * wall planes). LBM_EUNSUPPORTED for the D1V7 thermal model. lam: device float
  * buffer of adjoint_bytes. Starts a reverse pass: held dJ/dE, dJ/dtau contributions of
@@ -268,11 +297,17 @@ int lbm_adjoint_step(lbm_t h, const void *state, const float *lam_in, float *lam
  * uses it to set initial conditions and to report fields. */
 int lbm_density_from_mu(const lbm_params *p, const double *mu, double *rho, size_t n, void *stream);
 
-/* The inverse: mu from rho > 0 (closed form in 2D, Newton's method on g_3/2 in 3D).
+/* The inverse of the density relation of Sec. 9.1-9.2: mu from rho > 0 (closed form in
+ * 2D, Newton's method on g_3/2 in 3D, where the paper inverts it numerically).
  * NaN where no mu exists: rho <= 0, and Bose-Einstein 3D densities at or above
  * (pi theta)^(3/2) zeta(3/2) (condensation). Same arguments and errors as above. */
 int lbm_mu_from_density(const lbm_params *p, const double *rho, double *mu, size_t n, void *stream);
 
+/* Not in the paper (handle lifetime and error reporting of this library). lbm_destroy
+ * frees the host-side handle (NULL is a no-op) and no device memory, which the caller
+ * owns; lbm_last_error gives the message of the last failing call on h (h = NULL: of the
+ * last failing call that had no handle, on this thread); lbm_status_string names a
+ * status code. The strings are owned by the library. */
 void lbm_destroy(lbm_t h);
 const char *lbm_last_error(lbm_t h);
 const char *lbm_status_string(int status);

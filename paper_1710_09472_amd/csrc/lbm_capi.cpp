@@ -436,6 +436,11 @@ int lbm_buffer_sizes(const lbm_params *p, size_t *state_bytes, size_t *work_byte
     return LBM_OK;
 }
 
+int lbm_workspace_bytes(const lbm_params *p, size_t *state_bytes, size_t *work_bytes)
+{
+    return lbm_buffer_sizes(p, state_bytes, work_bytes, nullptr, nullptr);
+}
+
 int lbm_create(const lbm_params *p, const uint8_t *mask, const float *s, void *state_a, void *state_b, void *work,
                void *stream, lbm_t *out)
 {

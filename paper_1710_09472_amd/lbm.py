@@ -24,7 +24,8 @@ LBM_OK, LBM_EINVAL, LBM_EUNSUPPORTED, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 
 
 #: Every function the header declares (checked by the tests).
 EXPORTS = [
-    "lbm_compute_constants", "lbm_lattice_info", "lbm_buffer_sizes", "lbm_create", "lbm_init",
+    "lbm_compute_constants", "lbm_lattice_info", "lbm_workspace_bytes", "lbm_buffer_sizes", "lbm_create",
+    "lbm_init",
     "lbm_step", "lbm_step_from", "lbm_moments", "lbm_current", "lbm_get_state", "lbm_set_state",
     "lbm_export_f64", "lbm_set_fields", "lbm_set_tau", "lbm_adjoint_seed", "lbm_adjoint_step",
     "lbm_density_from_mu", "lbm_mu_from_density", "lbm_init_thermal", "lbm_thetabar", "lbm_energy",
@@ -75,6 +76,7 @@ def load_library() -> ctypes.CDLL:
         P = ctypes.POINTER(LbmParams)
         lib.lbm_compute_constants.argtypes = [P, ctypes.POINTER(LbmConstants)]
         lib.lbm_lattice_info.argtypes = [i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
+        lib.lbm_workspace_bytes.argtypes = [P, sz, sz]
         lib.lbm_buffer_sizes.argtypes = [P, sz, sz, sz, sz]
         lib.lbm_create.argtypes = [P, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
         lib.lbm_init.argtypes = [vp, vp, vp]

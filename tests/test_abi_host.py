@@ -179,6 +179,54 @@ def test_buffer_sizes():
     nwaves = 2 * 7 * 4  # ceil(300 / 256) 256-node tiles per row, 4 waves each
     assert s16["work"] >= 4 * st + 8 * 1024 * 5 + 32 * nwaves
 
+def test_workspace_bytes_matches_buffer_sizes():
+    """lbm_workspace_bytes (the size query of the boundary) reports the state and work
+    sizes of lbm_buffer_sizes and rejects what lbm_create rejects."""
+    lib = lbm.load_library()
+    for p in (lbm.make_params("D2V9", 4096, 4096), lbm.make_params("D3V19", 128, 128, 128, storage="f16"),
+              lbm.make_params("D2V9", 300, 7, storage="bf16")):
+        st, wk = ctypes.c_size_t(), ctypes.c_size_t()
+        assert lib.lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(st), ctypes.byref(wk)) == lbm.LBM_OK
+        ref = lbm.buffer_sizes(p)
+        assert (st.value, wk.value) == (ref["state"], ref["work"])
+        assert lib.lbm_workspace_bytes(ctypes.byref(p), None, None) == lbm.LBM_OK
+    bad = lbm.make_params("D2V9", 16, 8, tau=0.5)
+    assert lib.lbm_workspace_bytes(ctypes.byref(bad), None, None) == lbm.LBM_EINVAL
+    assert lib.lbm_workspace_bytes(None, None, None) == lbm.LBM_EINVAL
+
+
+# The calls of the boundary as the problem statement of the method names them: constants,
+# size query, create (lattice, grid, tau, E, B, mask), init, step, moments, current, the
+# adjoint step, state I/O, field and tau updates, teardown and errors.
+BOUNDARY_CALLS = ["lbm_workspace_bytes", "lbm_create", "lbm_init", "lbm_step", "lbm_moments", "lbm_current",
+                  "lbm_adjoint_step", "lbm_get_state", "lbm_set_state", "lbm_set_fields", "lbm_set_tau",
+                  "lbm_destroy", "lbm_last_error", "lbm_status_string"]
+
+
+def test_boundary_calls_declared_and_exported():
+    names = _header_functions()
+    lib = lbm.load_library()
+    for name in BOUNDARY_CALLS:
+        assert name in names and hasattr(lib, name), name
+
+
+def test_every_declaration_cites_a_passage():
+    """The comment above every function declaration of the header names the passage of the
+    paper that defines the operation (a section, equation, table or appendix) or says that
+    it is not in the paper."""
+    txt = open(HEADER).read()
+    body = txt[txt.index("extern \"C\" {"):]
+    blocks = re.findall(r"/\*(.*?)\*/\s*((?:(?:int|void|const char \*)\s*\*?lbm_[a-z0-9_]+\s*\([^;]*\);\s*)+)",
+                        body, flags=re.S)
+    seen = set()
+    for comment, decls in blocks:
+        fn = re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", decls)
+        cited = re.search(r"\b(Sec\.|eq\.|eqs\.|Table|App\.)", comment) or "not in the paper" in comment.lower()
+        assert cited, fn
+        seen.update(fn)
+    assert seen == set(_header_functions())
+
+
 def test_scheme_validation():
     """Forcing and free-slip parameters are validated on the host (no device work)."""
     lib = lbm.load_library()
