@@ -305,6 +305,82 @@ def cpu_baseline_thermal(wl, target_s: float = 12.0):
                       f"{dt:.1f} s", "cpu_model": model}
 
 
+def _window_plan(dims, steps: int, core: int, centre):
+    """Periodic sub-window holding the whole dependence cone of a core x core block after
+    `steps` steps: axes longer than the window are cut to core + 2 (steps + 1) nodes around
+    the block; shorter axes are kept whole. Returns (lo, size, block offset in the window)."""
+    lo, size, off = [], [], []
+    for i in range(3):
+        width = core + 2 * (steps + 1)
+        if dims[i] == 1 or width >= dims[i]:
+            lo.append(0), size.append(dims[i]), off.append(centre[i] if dims[i] > 1 else 0)
+        else:
+            lo.append(centre[i] - (steps + 1)), size.append(width), off.append(steps + 1)
+    return lo, size, off
+
+
+def oracle_blocks(wl, steps: int, core: int, centres):
+    """The FP64 oracle's rho and u after `steps` steps from the workload's initial state on
+    core x core blocks, each recomputed exactly on the periodic sub-window of its dependence
+    cone (the node update only reads the neighbours, so within `steps` steps the block does
+    not see the rest of the grid). Periodic workloads without solids or porosity only.
+    Returns (global node indices, rho, u (D, n))."""
+    import numpy as np
+
+    from oracle.oracle import OracleModel
+    from paper_1710_09472_amd import workloads as W
+
+    assert wl.mask is None and wl.s is None and not wl.slip
+    dims = (wl.nx, wl.ny, wl.nz)
+    idx, ref_rho, ref_u = [], [], []
+    for c in centres:
+        lo, size, off = _window_plan(dims, steps, core, c)
+        m = OracleModel(wl.lattice, *size, tau=wl.tau, E=wl.E, B=wl.B, forcing=wl.forcing)
+        rho_w = W.window(wl.rho, dims, lo, size)
+        u_w = None if wl.u is None else W.window(wl.u, dims, lo, size, ncomp=wl.D)
+        rho_o, u_o = m.moments(m.run(m.init_state(rho_w, u_w), steps))
+        cs = [min(core, size[i]) for i in range(3)]
+        loc = [(np.arange(cs[i]) + off[i]) % size[i] for i in range(3)]
+        glob = [(loc[i] + lo[i]) % dims[i] for i in range(3)]
+        li = (loc[0][None, None, :] + size[0] * (loc[1][None, :, None] + size[1] * loc[2][:, None, None])).reshape(-1)
+        gi = (glob[0][None, None, :] + dims[0] * (glob[1][None, :, None] + dims[1] * glob[2][:, None, None])).reshape(-1)
+        idx.append(gi), ref_rho.append(rho_o[li]), ref_u.append(u_o[:, li])
+    return np.concatenate(idx), np.concatenate(ref_rho), np.concatenate(ref_u, axis=1)
+
+
+def oracle_errors(wl, storages, steps: int = 100, core: int = 16,
+                  centres=((0, 0, 0), (2048, 2048, 0))):
+    """Max-norm errors of rho and u of the GPU step against the FP64 oracle (oracle_blocks)
+    after `steps` steps: max|gpu - oracle| over the blocks divided by the largest |rho|, and
+    the largest velocity component, of the oracle's blocks. storages: [(name, k)]."""
+    import numpy as np
+    import torch
+
+    from paper_1710_09472_amd.lbm import Simulation
+
+    t0 = time.perf_counter()
+    idx, ref_rho, ref_u = oracle_blocks(wl, steps, core, centres)
+    t_oracle = time.perf_counter() - t0
+    out = {}
+    for st, k in storages:
+        sim = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E, B=wl.B, storage=st, dev_scale_log2=k,
+                         forcing=wl.forcing)
+        sim.init(wl.rho, wl.u)
+        sim.step(steps)
+        rho, u = sim.moments()
+        torch.cuda.synchronize()
+        rho, u = rho.double().cpu().numpy()[idx], u.double().cpu().numpy()[:, idx]
+        sim.close()
+        er = float(np.abs(rho - ref_rho).max() / np.abs(ref_rho).max())
+        eu = float(np.abs(u - ref_u).max() / np.abs(ref_u).max())
+        out[st] = {"rho": float(f"{er:.3g}"), "u": float(f"{eu:.3g}")}
+        if st == "f16":
+            out[st]["dev_scale_log2"] = k
+    out["sample"] = (f"{len(centres)} blocks of {core}x{core} nodes at {[c[:2] for c in centres]} after {steps} steps, "
+                     f"oracle on their dependence-cone windows ({t_oracle:.1f} s); max-norm error / max|ref|")
+    return out
+
+
 def cpu_baseline(wl, target_s: float = 12.0):
     """The FP64 oracle on this host's cores on a slab of the same workload (the first
     256 rows of a 2D grid, the first planes of a 3D grid, about half a million nodes,
@@ -479,6 +555,10 @@ def main():
     out["mass_after_run"] = tot[0]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
+        if default:
+            # the stated error of each timed storage format: the oracle (FP64) against the
+            # GPU step in the same launch configuration, on sampled blocks after 100 steps
+            out["err"] = oracle_errors(wl, [("f32", 0), ("f16", F16_SCALE["throughput_2d"]), ("bf16", 0)])
     print(json.dumps(out), flush=True)
 
 

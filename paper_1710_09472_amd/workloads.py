@@ -30,6 +30,7 @@ The paper's own setups (Sec. 9.3, 9.4), with its velocity-shift forcing:
   balls of radius 3 (seed 5, porosity 0.974), E_x = 1e-7, tau = 0.9.
 * ``poiseuille_paper_2d``  D2V9 256x256, bounce-back rows y = 0, 255, periodic x,
   E_x = 1e-8, tau given (the paper sweeps five values), 10^6 steps.
+* ``poiseuille_paper_3d``  D3V19 256x256x1, the same channel, periodic in x and z.
 
 These use density 1 where the paper starts from mu = 1 (rho = I_0): the update is
 homogeneous of degree one in f, so the velocity field does not depend on that scale.
@@ -288,6 +289,14 @@ def ohm_paper_3d(Ex: float = 1e-7, seed: int = 5, steps: int = 20000) -> Workloa
 def poiseuille_paper_2d(tau: float = 0.8, n: int = 256, steps: int = 1_000_000) -> Workload:
     return Workload("poiseuille_paper_2d", "D2V9", n, n, 1, tau=tau, steps=steps, E=(1e-8, 0.0, 0.0),
                     rho=np.ones(n * n), mask=channel_mask_2d(n, n), forcing="shift")
+
+
+def poiseuille_paper_3d(tau: float = 0.8, n: int = 256, steps: int = 1_000_000) -> Workload:
+    """The 3D run of Sec. 9.3: D3V19 n x n x 1, bounce-back rows y = 0, n - 1, periodic in x
+    and z, velocity shift E_x = 1e-8."""
+    mask = channel_mask_2d(n, n)
+    return Workload("poiseuille_paper_3d", "D3V19", n, n, 1, tau=tau, steps=steps, E=(1e-8, 0.0, 0.0),
+                    rho=np.ones(n * n), mask=mask, forcing="shift")
 
 
 def thermal_1d(thetabar_ref: float, n: int = 1 << 24, seed: int = 6, tau: float = 0.8,

@@ -66,3 +66,22 @@ def test_traffic_only_for_the_code_it_was_taken_on(tmp_path, monkeypatch):
     assert np.isclose(bench.traffic_from_profile(tag), 1.25e9)
     (tmp_path / f"{tag}_pmc.txt").write_text("hbm_bytes_per_launch: 1.25e+09\nkernel_code_sha256: " + "0" * 64 + "\n")
     assert bench.traffic_from_profile(tag) is None
+
+
+def test_oracle_blocks_equal_the_full_grid_oracle(oracle_lib):
+    """The error figures of bench.py compare the GPU with the oracle on sampled blocks that the
+    oracle recomputes on the windows of their dependence cones: on a grid the oracle runs
+    whole, the blocks equal the full-grid run exactly (also where a window wraps around)."""
+    wl = W.throughput_2d(nx=96, ny=80, seed=3)
+    wl.u = 0.01 * np.random.default_rng(4).standard_normal((2, wl.N))
+    steps, core = 12, 8
+    centres = ((0, 0, 0), (90, 40, 0), (47, 79, 0))
+    idx, rho_b, u_b = bench.oracle_blocks(wl, steps, core, centres)
+    m = oracle_lib.OracleModel("D2V9", wl.nx, wl.ny, 1, tau=wl.tau)
+    rho, u = m.moments(m.run(m.init_state(wl.rho, wl.u), steps))
+    assert idx.size == len(centres) * core * core
+    np.testing.assert_array_equal(rho_b, rho[idx])
+    np.testing.assert_array_equal(u_b, u[:, idx])
+    # the block of centre (90, 40) holds x = 90..95 and 0..1 (wrapped), y = 40..47
+    b = idx[core * core:2 * core * core]
+    assert set(b % wl.nx) == set(range(90, 96)) | {0, 1} and set(b // wl.nx) == set(range(40, 48))

@@ -2,10 +2,12 @@
 
 * Poiseuille viscosity (Sec. 9.3): the 256x256 channel (bounce-back rows y = 0, 255,
   halfway walls at y = 0.5 and 254.5, H = 254) driven by the velocity shift with E = 1e-8,
-  10^6 steps for each of five relaxation times; a one-parameter parabola fit of the
-  x-averaged profile, u(y') = a y'(H - y') / (2 nu), gives nu within 1 % of (tau - 1/2)/3,
-  the relation the paper reports. (10^6 steps leave the slowest start-up mode at
-  exp(-pi^2 nu t / H^2) < 1e-6 for these tau.)
+  10^6 steps for each of five relaxation times, with the 2D model (D2V9) and with the 3D
+  model on the 256x256x1 grid periodic in x and z (D3V19); a one-parameter parabola fit of
+  the x-averaged profile, u(y') = a y'(H - y') / (2 nu), gives nu within 1 % of
+  (tau - 1/2)/3, the relation the paper reports for both models (and the oracle pins).
+  (10^6 steps leave the slowest start-up mode at exp(-pi^2 nu t / H^2) < 1e-6 for these
+  tau.)
 * Ohm's law (Sec. 9.4): the 512x256 sample (64 disks of radius 3, free-slip walls y,
   velocity shift, tau = 0.9) after 20000 steps: <u_x>/E is the same within 1 % over
   E = 1..8 x 1e-7, the linear relation the paper plots. It is not constant to rounding:
@@ -21,9 +23,10 @@ from parity_helpers import gpu_fields, gpu_sim
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("lattice", ["D2V9", "D3V19"])
 @pytest.mark.parametrize("tau", [0.8, 1.0, 1.2, 1.5, 2.0])
-def test_paper_poiseuille_viscosity(tau):
-    wl = W.poiseuille_paper_2d(tau=tau)
+def test_paper_poiseuille_viscosity(tau, lattice):
+    wl = W.poiseuille_paper_2d(tau=tau) if lattice == "D2V9" else W.poiseuille_paper_3d(tau=tau)
     sim = gpu_sim(wl)
     sim.step(wl.steps)
     rho, u = gpu_fields(sim)
@@ -37,7 +40,9 @@ def test_paper_poiseuille_viscosity(tau):
     nu_fit = wl.E[0] / (2 * alpha)
     nu = (tau - 0.5) / 3.0
     resid = np.linalg.norm(prof - alpha * shape) / np.linalg.norm(prof)
-    print(f"tau {tau}: nu fit {nu_fit:.6e}, (tau - 1/2)/3 = {nu:.6e}, ratio {nu_fit / nu:.5f}, "
+    if lattice == "D3V19":
+        assert np.abs(u[2]).max() < 1e-5 * np.abs(prof).max()
+    print(f"{lattice} tau {tau}: nu fit {nu_fit:.6e}, (tau - 1/2)/3 = {nu:.6e}, ratio {nu_fit / nu:.5f}, "
           f"parabola residual {resid:.2e}")
     assert abs(nu_fit / nu - 1) < 1e-2
     assert resid < 1e-3

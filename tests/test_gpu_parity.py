@@ -74,16 +74,13 @@ def test_poiseuille_full_parity():
 
 
 def test_riemann_full_parity():
-    """Shock tube 4096x4 with closed ends, 1500 steps, element-wise.
-
-    rho meets the 1e-5 max-norm bar and u meets it in the L2 norm. The max-norm of u is
-    held to 1e-4: at the shock front the solution jumps by ~0.03 of max|u| per cell, so
-    the random sub-ulp rounding of FP32 deviation storage (ulp 3.7e-9 of the stored
-    values here, every population every step) moves the front by a few 1e-5 cells over
-    1500 steps. Re-running the FP64 oracle with its deviations rounded to FP32 after every
-    step (FP64 arithmetic otherwise) gives max-norm u errors of 1e-5 to 6e-5 depending
-    on the rounding pattern, so 1e-5 in the max-norm of u is below the storage floor of
-    this workload."""
+    """Shock tube 4096x4 with closed ends, 1500 steps, element-wise: rho and u within 1e-5
+    in the max-norm (measured 1.4e-6 and 8.3e-6, both largest at the shock front), and u
+    within 1e-5 in the L2 norm. At the front the solution jumps by ~0.03 of max|u| per cell,
+    so the max-norm of u measures the front position: the oracle run again with its
+    deviations rounded to FP32 after every step moves the front by up to ~2e-4 of max|u|
+    (test_oracle_storage_floor), so this bound holds for this kernel's rounding, not for
+    FP32 deviation storage in general."""
     wl = W.riemann_2d()
     sim = gpu_sim(wl)
     sim.step(wl.steps)
@@ -97,7 +94,7 @@ def test_riemann_full_parity():
     print(f"riemann 1500 steps: rel err rho {er:.3e} (x={xr}), u max {eu:.3e} (x={xu}), u L2 {l2u:.3e}")
     assert er < TOL, er
     assert l2u < TOL, l2u
-    assert eu < 1e-4, eu
+    assert eu < TOL, eu
 
 
 def _window_check(wl, steps, centres, core, storage="f32", tol=TOL):

@@ -140,8 +140,15 @@ def test_16bit_error_full_grid(name, builder, steps, bounds):
             assert ec < bc, (st, ec)
 
 
+# The 4096^2 grid is checked at the FP16 scale the benchmark times it with (2^12; its initial
+# deviations reach ~0.03, so 2^12 keeps them below FP16's largest value with headroom, while
+# every deviation after 100 steps stays in FP16's normal range), in the benchmark's launch
+# configuration: the errors the benchmark states.
+F16_SCALE_BENCH = 12
 SAMPLED = [
     ("throughput_4096sq", W.throughput_2d, 100, [(0, 0, 0), (2048, 2048, 0)], 16,
+     {"f16": (1e-5, 3e-3), "bf16": (1e-4, 2e-2)}),
+    ("throughput_4096sq_calibrated_k", W.throughput_2d, 100, [(2048, 2048, 0)], 16,
      {"f16": (1e-5, 3e-3), "bf16": (1e-4, 2e-2)}),
     ("hall_duct_3d", W.hall_duct_3d, 30, [(0, 0, 0), (128, 64, 64)], 6, {"f16": (1e-6, 1e-3), "bf16": (1e-6, 5e-3)}),
     ("soft_porous_3d", W.soft_porous_3d, 30, [(64, 64, 64)], 6, {"f16": (1e-6, 1e-3), "bf16": (1e-6, 5e-3)}),
@@ -153,7 +160,7 @@ SAMPLED = [
 @pytest.mark.parametrize("name,builder,steps,centres,core,bounds", SAMPLED, ids=[c[0] for c in SAMPLED])
 def test_16bit_error_sampled(name, builder, steps, centres, core, bounds):
     wl = builder()
-    k = _f16_scale(wl, steps)
+    k = F16_SCALE_BENCH if name == "throughput_4096sq" else _f16_scale(wl, steps)
     ref = [oracle_window_fields(wl, steps, core, c) for c in centres]
     res = {}
     for st in ("f32", "f16", "bf16"):
