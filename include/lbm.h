@@ -228,6 +228,20 @@ int lbm_energy(lbm_t h, double *out);
  * memory. Synchronises the stream. LBM_ENONFINITE if any total is NaN/Inf. */
 int lbm_current(lbm_t h, double out[4]);
 
+/* For callers that cannot allocate device memory or synchronise (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the totals of
+ * lbm_current, computed the same way (same kernels, same FP64 reduction order, the same
+ * bits), written asynchronously into device memory out[4] = (sum rho, sum rho u) on the
+ * handle's stream. The reduction partials live in a fixed device-resident scratch array of
+ * the library (64 KiB per GPU, held until the process ends; the totals use 57 KiB whatever
+ * the grid size, LBM_EINVAL if that ever exceeded the array) instead of the workspace; no
+ * hipMalloc, hipFree, memset or host synchronisation. Every call on one GPU shares that
+ * GPU's array, and each call overwrites every part of it that it reads, so calls that
+ * overlap on one GPU (concurrent streams or threads) race and must be serialised by the
+ * caller. No NaN/Inf check (that needs the host): non-finite totals arrive as such.
+ * D2V9 and D3V19 only (LBM_EUNSUPPORTED for D1V7). out: device double[4]. */
+int lbm_current_noalloc(lbm_t h, double *out);
+
 /* Convergence measure of the Ohm's-law runs (Sec. 9.4, stopped when it falls below 1e-7):
  * the average, over the nodes whose speed |u_new| is non-zero (fluid nodes; solids have
  * u = 0), of | |u_new| - |u_old| | / |u_new|. u (device float[D*N], the layout lbm_moments

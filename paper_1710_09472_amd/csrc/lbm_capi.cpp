@@ -789,6 +789,35 @@ int lbm_current(lbm_t h, double out[4])
     return LBM_OK;
 }
 
+int lbm_current_noalloc(lbm_t h, double *out)
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    if (!out) return fail(h, LBM_EINVAL, "out is required");
+    if (!h->initialized) return fail(h, LBM_ESTATE, "lbm_current_noalloc before lbm_init or lbm_set_state");
+    if (h->thermal) return fail(h, LBM_EUNSUPPORTED, "lbm_current_noalloc covers the D2V9 and D3V19 lattices");
+    int device = 0;
+    hipError_t e = h->stream ? hipStreamGetDevice(h->stream, &device) : hipGetDevice(&device);
+    if (e != hipSuccess) return hip_fail(h, e, "device of the handle's stream");
+    double *scratch = nullptr;
+    size_t bytes = 0;
+    e = static_scratch(device, &scratch, &bytes);
+    if (e != hipSuccess) return hip_fail(h, e, "address of the static scratch array");
+    if (totals_scratch_bytes() > bytes)
+        return fail(h, LBM_EINVAL, "the totals reduction needs %zu bytes of scratch, above the %zu of the static array",
+                    totals_scratch_bytes(), bytes);
+    GatherArgs a{};
+    a.g = h->g;
+    a.ph = h->ph;
+    a.links = links_of(h);
+    a.src = h->buf[h->cur];
+    a.N = h->N;
+    a.odd = (h->aa && h->parity) ? 1 : 0;
+    for (int k = 0; k < 4; ++k) a.what_rho0[k] = h->k.what[k] * h->p.rho0;
+    e = launch_totals_noalloc(h->p.lattice, h->p.storage, a, h->p.rho0, h->k.cs, out, h->stream, scratch);
+    if (e != hipSuccess) return hip_fail(h, e, "totals kernel launch");
+    return LBM_OK;
+}
+
 int lbm_get_state(lbm_t h, void *dst)
 {
     if (!h) return fail(nullptr, LBM_EINVAL, "null handle");

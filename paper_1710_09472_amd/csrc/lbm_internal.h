@@ -201,6 +201,12 @@ hipError_t launch_gather(int lattice, int storage, const GatherArgs &a, int nblo
 // Sum per-block partials [nparts][ncomp] (ncomp <= 8) into out (+= if accumulate).
 // `stage` (kReduceStage * ncomp doubles, nullable) enables a two-stage reduction.
 // Convergence measure of Sec. 9.4 (lbm_speed_change): per-block partials [block][2]
+// Device address (per device, looked up once) and size of the library's static scratch
+// array, and the FP64 totals of lbm_current reduced through it into device out[4].
+hipError_t static_scratch(int device, double **ptr, size_t *bytes);
+size_t totals_scratch_bytes();
+hipError_t launch_totals_noalloc(int lattice, int storage, const GatherArgs &a, double rho0, double cs, double *out,
+                                 hipStream_t st, double *scratch_dev);
 hipError_t launch_speed_change(const float *u, int D, int N, float *speed, int have_prev, double *partials,
                                int nblocks, hipStream_t st);
 hipError_t launch_reduce_final(const double *partials, int nparts, int ncomp, double *out,

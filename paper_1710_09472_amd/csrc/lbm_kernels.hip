@@ -20,6 +20,7 @@
 #include "lbm_device.h"
 
 #include <cstdlib>
+#include <mutex>
 
 namespace lbm {
 
@@ -904,6 +905,83 @@ hipError_t launch_reduce_final(const double *partials, int nparts, int ncomp, do
         nparts = kReduceStage;
     }
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, st, partials, nparts, ncomp, out, accumulate);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Totals without a workspace: the reduction partials of lbm_current_noalloc live in a
+// fixed device-resident array of this file instead of the caller's workspace. Its host
+// name is only a stand-in: host code uses the device address that hipGetSymbolAddress
+// returns, looked up once per device with that device current.
+// ---------------------------------------------------------------------------------
+namespace {
+
+// parts [kReduceBlocks][5] | stage [kReduceStage][8] | sums [8]
+constexpr size_t kScratchParts = 0;
+constexpr size_t kScratchStage = kScratchParts + (size_t)kReduceBlocks * 5;
+constexpr size_t kScratchSums = kScratchStage + (size_t)kReduceStage * 8;
+constexpr size_t kScratchUsed = kScratchSums + 8;
+constexpr size_t kScratchDoubles = 8192;  // 64 KiB per device
+static_assert(kScratchUsed <= kScratchDoubles, "static scratch too small for the totals reduction");
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// out = (nfluid rho0 + sum drho, sum j / c_s) from the sums (sum drho, sum j_x, sum j_y,
+// sum j_z, nfluid), the same FP64 operations as lbm_current performs on the host.
+__global__ void k_totals_finish(const double *__restrict__ sums, double rho0, double cs, double *__restrict__ out)
+{
+#pragma clang fp contract(off)
+    const int i = (int)threadIdx.x;
+    if (i == 0) out[0] = sums[4] * rho0 + sums[0];
+    if (i >= 1 && i < 4) out[i] = sums[i] / cs;
+}
+
+}  // namespace
+
+hipError_t static_scratch(int device, double **ptr, size_t *bytes)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return e;
+        if (prev != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev != device) {
+            const hipError_t e2 = hipSetDevice(prev);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = static_cast<double *>(p);
+    }
+    *ptr = g_scratch_ptr[device];
+    *bytes = kScratchDoubles * sizeof(double);
+    return hipSuccess;
+}
+
+size_t totals_scratch_bytes() { return kScratchUsed * sizeof(double); }
+
+hipError_t launch_totals_noalloc(int lattice, int storage, const GatherArgs &a, double rho0, double cs, double *out,
+                                 hipStream_t st, double *scratch_dev)
+{
+    if (!out || !scratch_dev) return hipErrorInvalidValue;
+    GatherArgs b = a;
+    b.rho = b.u = nullptr;
+    b.f64 = nullptr;
+    b.partials = scratch_dev + kScratchParts;
+    hipError_t e = launch_gather(lattice, storage, b, kReduceBlocks, st);
+    if (e != hipSuccess) return e;
+    e = launch_reduce_final(scratch_dev + kScratchParts, kReduceBlocks, 5, scratch_dev + kScratchSums, 0, st,
+                            scratch_dev + kScratchStage);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_totals_finish, dim3(1), dim3(64), 0, st, scratch_dev + kScratchSums, rho0, cs, out);
     return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ EXPORTS = [
     "lbm_step", "lbm_step_from", "lbm_moments", "lbm_current", "lbm_get_state", "lbm_set_state",
     "lbm_export_f64", "lbm_set_fields", "lbm_set_tau", "lbm_adjoint_seed", "lbm_adjoint_step",
     "lbm_density_from_mu", "lbm_mu_from_density", "lbm_init_thermal", "lbm_thetabar", "lbm_energy",
-    "lbm_speed_change", "lbm_destroy", "lbm_last_error", "lbm_status_string",
+    "lbm_speed_change", "lbm_destroy", "lbm_last_error", "lbm_status_string", "lbm_current_noalloc",
 ]
 
 
@@ -88,6 +88,7 @@ def load_library() -> ctypes.CDLL:
         lib.lbm_step_from.argtypes = [vp, vp, vp]
         lib.lbm_moments.argtypes = [vp, vp, vp]
         lib.lbm_current.argtypes = [vp, ctypes.POINTER(d)]
+        lib.lbm_current_noalloc.argtypes = [vp, vp]
         lib.lbm_get_state.argtypes = [vp, vp]
         lib.lbm_set_state.argtypes = [vp, vp]
         lib.lbm_export_f64.argtypes = [vp, vp, vp]
@@ -315,6 +316,15 @@ class Simulation:
         out = (ctypes.c_double * 4)()
         _check(self.lib.lbm_current(self.h, out), self.h)
         return np.array(out[:])
+
+    def current_noalloc(self, out=None):
+        """The totals of current() into a float64 (4,) device tensor, asynchronously, with
+        the reduction in the library's static scratch (lbm_current_noalloc: no workspace,
+        allocation or synchronisation inside the call)."""
+        if out is None:
+            out = self.torch.empty(4, dtype=self.torch.float64, device=self.device)
+        _check(self.lib.lbm_current_noalloc(self.h, _ptr(out)), self.h)
+        return out
 
     def speed_change(self, u, speed, have_previous=True):
         """Convergence measure of Sec. 9.4 (lbm_speed_change): the average over nodes with
