@@ -447,6 +447,8 @@ def main():
                     help="time the in-place step (one state buffer) instead of the two-buffer step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB three times with a plain device copy (reference for HBM counters)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the checkpointed adjoint of the 128^3 soft-porosity workload (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the method runs on a "
@@ -464,6 +466,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_pipeline()}), flush=True)
+        return
 
     wl = make_workload(args.workload)
     N = wl.N

@@ -47,8 +47,9 @@ def build(verbose: bool = False) -> Path:
     for src in SOURCES:
         obj = BUILD / (src.replace(".", "_") + ".o")
         objs.append(obj)
-        lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = [hipcc(), *compile_flags(), *lang, "-c", str(CSRC / src), "-o", str(obj)]
+        # every source, .cpp included, is compiled as HIP: the host files include the HIP
+        # runtime header through lbm_internal.h, and one language keeps one set of flags
+        cmd = [hipcc(), *compile_flags(), "-x", "hip", "-c", str(CSRC / src), "-o", str(obj)]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))

@@ -16,6 +16,23 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-4
 
+
+def check_dtau(g_tau, ref_tau, tau, E, gE, what=""):
+    """dJ/dtau against the oracle's on its own scale (1e-4 relative). Where the oracle's
+    dJ/dtau vanishes to rounding (a uniform state, plug flow between free-slip planes: J
+    does not depend on the viscosity), there is no scale of its own; the bound is then on the
+    logarithmic sensitivity, |tau dJ/dtau| <= 1e-6 |E . dJ/dE| (both in units of J), i.e. the
+    GPU's d ln J / d ln tau stays within 1e-6 of d ln J / d ln E, which is ~1."""
+    gE_scale = abs(float(np.dot(np.asarray(E, float)[:len(gE)], np.asarray(gE, float))))
+    vanishing = abs(tau * ref_tau) <= 1e-9 * gE_scale
+    print(f"{what}dJ/dtau adjoint {g_tau:.9e} oracle {ref_tau:.9e} "
+          + (f"(vanishes: tau dJ/dtau / E.dJ/dE = {abs(tau * g_tau) / gE_scale:.1e})" if vanishing
+             else f"rel {abs(g_tau / ref_tau - 1):.2e}"))
+    if vanishing:
+        assert abs(tau * g_tau) <= 1e-6 * gE_scale, (g_tau, ref_tau)
+    else:
+        assert abs(g_tau - ref_tau) <= TOL * abs(ref_tau), (g_tau, ref_tau)
+
 CASES = [
     # name, lattice, shape, obstacle fraction, soft, E, B, tau, free-slip planes[, forcing]
     ("d3-soft", "D3V19", (20, 9, 7), 0.0, True, (1e-3, -4e-4, 2e-4), (0, 0, 0), 0.75, 0),
@@ -89,7 +106,7 @@ def _check_against_oracle(wl, T, axis=0):
     big = np.abs(g_o[:wl.D]).max()  # a vanishing component is compared on this scale
     for i in range(wl.D):
         assert abs(g[i] - g_o[i]) <= TOL * max(abs(g_o[i]), 1e-4 * big), (i, g[i], g_o[i])
-    assert abs(g[3] - g_o[3]) <= TOL * max(abs(g_o[3]), 1e-3 * np.abs(g_o[:wl.D]).max()), (g[3], g_o[3])
+    check_dtau(g[3], g_o[3], wl.tau, wl.E, g_o[:wl.D], f"dJ/dE {g[:wl.D]} oracle {g_o[:wl.D]}; ")
     if wl.s is not None:
         gsv = gs.double().cpu().numpy()
         err_s = np.abs(gsv - gs_o).max() / np.abs(gs_o).max()
@@ -320,7 +337,7 @@ def test_autograd_checkpointed_vs_oracle_fd():
         assert abs(E.grad[i].item() - fd) <= TOL * abs(fd), (i, E.grad[i].item(), fd)
     h = 1e-5
     fd = (J_or(wl.E, wl.tau + h, s64) - J_or(wl.E, wl.tau - h, s64)) / (2 * h)
-    assert abs(tau.grad.item() - fd) <= TOL * max(abs(fd), 1e-2 * abs(E.grad[0].item())), (tau.grad.item(), fd)
+    check_dtau(tau.grad.item(), fd, wl.tau, wl.E, E.grad.cpu().numpy(), "(oracle: central difference) ")
     v = np.random.default_rng(4).standard_normal(wl.N)
     h = 1e-5
     fd = (J_or(wl.E, wl.tau, s64 + h * v) - J_or(wl.E, wl.tau, s64 - h * v)) / (2 * h)
@@ -383,7 +400,7 @@ def test_schemes_autograd_vs_oracle_fd(case):
         assert abs(E.grad[i].item() - fd) <= TOL * max(abs(fd), 1e-4 * big), (i, E.grad[i].item(), fd)
     h = 1e-5
     fd = (J_or(wl.E, wl.tau + h, s64) - J_or(wl.E, wl.tau - h, s64)) / (2 * h)
-    assert abs(tau.grad.item() - fd) <= TOL * max(abs(fd), 1e-2 * abs(E.grad[0].item())), (tau.grad.item(), fd)
+    check_dtau(tau.grad.item(), fd, wl.tau, wl.E, E.grad.cpu().numpy(), "(oracle: central difference) ")
     if soft:
         v = np.random.default_rng(5).standard_normal(wl.N)
         fd = (J_or(wl.E, wl.tau, s64 + h * v) - J_or(wl.E, wl.tau, s64 - h * v)) / (2 * h)

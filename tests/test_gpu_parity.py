@@ -57,9 +57,11 @@ def test_small_parity_fields_and_populations(name, case):
     # totals in FP64 against the oracle's
     tot = sim.current()
     tot_o = m.totals(f_o, wl.mask)
-    assert abs(tot[0] / tot_o[0] - 1) < 1e-6
     scale = max(np.abs(tot_o[1:]).max(), 1e-30)
-    assert np.abs(tot[1:] - tot_o[1:]).max() / scale < 1e-4
+    eM, eP = abs(tot[0] / tot_o[0] - 1), np.abs(tot[1:] - tot_o[1:]).max() / scale
+    print(f"{name}: totals M {eM:.2e}, P {eP:.2e} (relative to max|P_i|)")
+    assert eM < 1e-6
+    assert eP < TOL
 
 
 def test_poiseuille_full_parity():
