@@ -69,39 +69,40 @@ __device__ __forceinline__ void store_pair_shifted(uint16_t *row, const PullRows
 // V nodes per thread as in the two-buffer step (same node arithmetic, same bits). The
 // stores of x-shifted populations are shifted like their loads: one value at a time,
 // or, with 16-bit storage and two nodes per thread, one 4-byte store per pair.
-template <int LAT, int ST, bool MASK, bool SOFT, int FORCE, int V>
+template <int LAT, int ST, bool MASK, bool SOFT, int FORCE, int V, bool SLIP>
 __global__ __launch_bounds__(kBlock) void k_step_aa_pull(StepArgs a, int ntx, FastDiv div_ntx, int nblocks)
 {
     using L = Lat<LAT>;
     using T = typename Codec<ST>::T;
     using LT = typename LinkMask<LAT>::T;
+    if constexpr (MASK && !SLIP) a.g.slip = 0;  // no free-slip planes: reflections compiled out
     const int bid = a.remap ? xcd_remap((int)blockIdx.x, nblocks) : (int)blockIdx.x;
     const Tile t = tile_of<V>(a.g, bid, ntx, div_ntx);
     if (!t.valid) return;
-    // 16-bit storage, two nodes per thread: a pair with one obstacle node is stored
-    // whole, and a wave leaves only when all its nodes are solid, so obstacle nodes take
-    // part like fluid ones: under the solid-slot convention the locations an obstacle node
-    // pulls from (and so stores to) are read and written by no fluid node. Nodes of
-    // free-slip wall planes are not like that, but they fill whole rows, so their waves
-    // leave as a whole.
+    // Rows of free-slip wall planes are solid as a whole: their blocks leave at once (a
+    // wave-uniform test on the row, no memory access). Every other solid node takes part in
+    // the loads and the collision, so that no lane waits for its link mask before its
+    // population loads issue, and only fluid nodes store; except that with 16-bit storage
+    // and two nodes per thread pairs are stored whole, obstacle nodes included: under the
+    // solid-slot convention the locations an obstacle node pulls from (and so stores to)
+    // are read and written by no fluid node (the index-map emulation of the host tests
+    // checks this, for waves of obstacles only too). Wall-plane nodes are not like that,
+    // which is why their rows leave.
     constexpr bool kPairs = ST != LBM_F32 && V == 2;
     static_assert(!kPairs || kSolidSlotBB<ST>, "pair stores rely on the solid-slot convention");
+    if (MASK && a.g.slip &&
+        (((a.g.slip & LBM_SLIP_Y) && (t.y == 0 || t.y == a.g.ny - 1)) ||
+         ((a.g.slip & LBM_SLIP_Z) && (t.z == 0 || t.z == a.g.nz - 1))))
+        return;
     LT lk[V];
     bool fluid[V];
     bool all_fluid = true;
     if (MASK) {
         load_links<LAT, V>(static_cast<const LT *>(a.links), t.own, lk);
-        bool any_fluid = false;
 #pragma unroll
         for (int i = 0; i < V; ++i) {
             fluid[i] = !(lk[i] & LinkMask<LAT>::solid);
-            any_fluid = any_fluid || fluid[i];
             all_fluid = all_fluid && fluid[i];
-        }
-        if constexpr (kPairs) {
-            if (__builtin_amdgcn_ballot_w64(any_fluid) == 0) return;  // wave-uniform
-        } else {
-            if (!any_fluid) return;
         }
     } else {
 #pragma unroll
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_pull(StepArgs a, int ntx, Fa
             if (!fluid[i]) continue;
             T *p;
             if (MASK && !kSolidSlotBB<ST> && ((lk[i] >> qb) & 1u))
-                p = at32(f + (size_t)q * a.g.stride, (unsigned)t.own + i);  // bounced: slot q of x
+                p = at32(f + slot_off(q, a.g.stride), (unsigned)t.own + i);  // bounced: slot q of x
             else
                 p = at32(row, pull_x<LAT, qb, V>(r, i));
             vstore<ST, 1>(p, 1.f, &o[i][q]);
@@ -155,23 +156,20 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_pull(StepArgs a, int ntx, Fa
 }
 
 // Phase 1: read the streamed populations of the node, collide, store in place.
-template <int LAT, int ST, bool MASK, bool SOFT, int FORCE, int V>
+template <int LAT, int ST, bool MASK, bool SOFT, int FORCE, int V, bool SLIP>
 __global__ __launch_bounds__(kBlock) void k_step_aa_local(StepArgs a, int ntx, FastDiv div_ntx, int nblocks)
 {
     using L = Lat<LAT>;
     using T = typename Codec<ST>::T;
     using LT = typename LinkMask<LAT>::T;
+    if constexpr (MASK && !SLIP) a.g.slip = 0;
     const int bid = a.remap ? xcd_remap((int)blockIdx.x, nblocks) : (int)blockIdx.x;
     const Tile t = tile_of<V>(a.g, bid, ntx, div_ntx);
     if (!t.valid) return;
+    // solid nodes load and collide too (their own slots, in bounds) and store nothing:
+    // no lane waits for its link mask before its loads issue
     LT lk[V];
-    if (MASK) {
-        load_links<LAT, V>(static_cast<const LT *>(a.links), t.own, lk);
-        bool any_fluid = false;
-#pragma unroll
-        for (int i = 0; i < V; ++i) any_fluid = any_fluid || !(lk[i] & LinkMask<LAT>::solid);
-        if (!any_fluid) return;
-    }
+    if (MASK) load_links<LAT, V>(static_cast<const LT *>(a.links), t.own, lk);
     T *f = static_cast<T *>(a.dst);
     float d[V][L::Q];
     gather_odd<LAT, ST, MASK, V>(a.g, f, 1.f, t, lk, d);
@@ -206,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_canon(StepArgs a)
     T *dst = static_cast<T *>(a.dst);
 #pragma unroll
     for (int q = 0; q < L::Q; ++q)
-        *at32(dst + (size_t)q * a.g.stride, (unsigned)t.own) = Codec<ST>::enc(d[0][L::opp[q]], 1.f);
+        *at32(dst + slot_off(q, a.g.stride), (unsigned)t.own) = Codec<ST>::enc(d[0][L::opp[q]], 1.f);
     if constexpr (MASK && kSolidSlotBB<ST>) {
         if (lk[0]) {
             const PullRows r = pull_rows<1>(a.g, t);
@@ -228,12 +226,20 @@ hipError_t aa_v(int force, int phase, const StepArgs &a, hipStream_t st)
     const int ntx = (a.g.nx + kBlock * V - 1) / (kBlock * V);
     const int nblocks = ntx * a.g.ny * a.g.nz;
     const FastDiv div_ntx = make_fastdiv(ntx);
-    const dim3 grid(nblocks), block(kBlock);
-#define LBM_AA(M, S, F)                                                                                            \
+    const dim3 grid(nblocks), block(row_block_threads(a.g.nx, V));
+#define LBM_AA_SL(M, S, F, SL)                                                                                     \
     if (phase == 0)                                                                                               \
-        hipLaunchKernelGGL((k_step_aa_pull<LAT, ST, M, S, F, V>), grid, block, 0, st, a, ntx, div_ntx, nblocks); \
+        hipLaunchKernelGGL((k_step_aa_pull<LAT, ST, M, S, F, V, SL>), grid, block, 0, st, a, ntx, div_ntx, nblocks); \
     else                                                                                                          \
-        hipLaunchKernelGGL((k_step_aa_local<LAT, ST, M, S, F, V>), grid, block, 0, st, a, ntx, div_ntx, nblocks)
+        hipLaunchKernelGGL((k_step_aa_local<LAT, ST, M, S, F, V, SL>), grid, block, 0, st, a, ntx, div_ntx, nblocks)
+#define LBM_AA(M, S, F)           \
+    do {                          \
+        if (M && a.g.slip) {      \
+            LBM_AA_SL(M, S, F, M);     \
+        } else {                  \
+            LBM_AA_SL(M, S, F, false); \
+        }                         \
+    } while (0)
 #define LBM_AA_F(M, S)     \
     if (force == 0)        \
         LBM_AA(M, S, 0);   \
@@ -250,6 +256,7 @@ hipError_t aa_v(int force, int phase, const StepArgs &a, hipStream_t st)
     }
 #undef LBM_AA_F
 #undef LBM_AA
+#undef LBM_AA_SL
     return hipGetLastError();
 }
 

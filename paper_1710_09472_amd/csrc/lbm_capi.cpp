@@ -931,7 +931,8 @@ int lbm_adjoint_step(lbm_t h, const void *state, const float *lam_in, float *lam
     if (e != hipSuccess) return hip_fail(h, e, "adjoint kernel launch");
     h->adj_held = true;
     if (grad_scalars) {
-        e = launch_reduce_final(work_adj(h), h->g.nblocks * (kBlock / 64), 4, grad_scalars, 1, h->stream,
+        e = launch_reduce_final(work_adj(h), h->g.nblocks * (row_block_threads(h->g.nx, 1) / 64), 4, grad_scalars, 1,
+                                h->stream,
                                 work_stage(h));
         if (e != hipSuccess) return hip_fail(h, e, "reduce kernel launch");
         h->adj_held = false;

@@ -113,6 +113,11 @@ __device__ __forceinline__ void vstore(typename Codec<ST>::T *p, float scale, co
     }
 }
 
+// Element offset of slot q (the start of population array q). Every element offset of a
+// state or adjoint field fits in 32 bits (Q * stride < 2^31 is checked at create), so the
+// products are formed in 32-bit arithmetic and only widened for the final address.
+__device__ __forceinline__ size_t slot_off(int q, int stride) { return (size_t)((unsigned)q * (unsigned)stride); }
+
 // base + idx elements with the byte offset formed in 32 bits, so that a load or store
 // takes the uniform base in SGPRs and one VGPR offset instead of a 64-bit lane address.
 // Every array indexed this way is below 4 GiB (Q * stride < 2^31 elements).
@@ -282,7 +287,7 @@ __device__ __forceinline__ size_t pull_row(const Geometry &g, const Tile &t, con
         constexpr int pyz = reflected<LAT>(q, true, true);
         p = fy ? (fz ? pyz : py) : (fz ? pz : q);
     }
-    return (size_t)p * g.stride + (size_t)g.nx * (sy + g.ny * sz);
+    return (size_t)((unsigned)p * (unsigned)g.stride + (unsigned)g.nx * (unsigned)(sy + g.ny * sz));
 }
 
 template <int LAT, int q, int V>
@@ -371,7 +376,7 @@ __device__ __forceinline__ void gather_tile(const Geometry &g, const typename Co
 #pragma unroll
                 for (int q = 1; q < L::Q; ++q)
                     if ((lk[i] >> q) & 1u)
-                        d[i][q] = Codec<ST>::dec(*at32(src + (size_t)L::opp[q] * g.stride, own + i), inv_scale);
+                        d[i][q] = Codec<ST>::dec(*at32(src + slot_off(L::opp[q], g.stride), own + i), inv_scale);
             }
         }
     }
@@ -399,7 +404,7 @@ __device__ __forceinline__ void gather_odd(const Geometry &g, const typename Cod
             const PullRows r = pull_rows<V>(g, t);
             for_q<L::Q>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
-                const unsigned own = (unsigned)((size_t)L::opp[q] * g.stride) + (unsigned)t.own;
+                const unsigned own = (unsigned)L::opp[q] * (unsigned)g.stride + (unsigned)t.own;
                 const unsigned row = (unsigned)pull_row<LAT, q>(g, t, r);
 #pragma unroll
                 for (int i = 0; i < V; ++i) {
@@ -413,7 +418,7 @@ __device__ __forceinline__ void gather_odd(const Geometry &g, const typename Cod
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
         float f[V];
-        vload<ST, V>(at32(src + (size_t)L::opp[q] * g.stride, (unsigned)t.own), inv_scale, f);
+        vload<ST, V>(at32(src + slot_off(L::opp[q], g.stride), (unsigned)t.own), inv_scale, f);
 #pragma unroll
         for (int i = 0; i < V; ++i) d[i][q] = f[i];
     }
@@ -642,7 +647,7 @@ __device__ __forceinline__ void store_tile(const Geometry &g, typename Codec<ST>
     }
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
-        T *p = at32(dst + (size_t)q * g.stride, (unsigned)t.own);
+        T *p = at32(dst + slot_off(q, g.stride), (unsigned)t.own);
         if (!MASK || all_fluid) {
             float f[V];
 #pragma unroll

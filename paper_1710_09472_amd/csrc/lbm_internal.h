@@ -201,6 +201,11 @@ hipError_t launch_gather(int lattice, int storage, const GatherArgs &a, int nblo
 // Sum per-block partials [nparts][ncomp] (ncomp <= 8) into out (+= if accumulate).
 // `stage` (kReduceStage * ncomp doubles, nullable) enables a two-stage reduction.
 // Convergence measure of Sec. 9.4 (lbm_speed_change): per-block partials [block][2]
+// Threads per block of the node kernels (k_step, the in-place phases, the adjoint) for rows
+// of nx nodes at V nodes per thread: kBlock, or, where one block covers a whole row, the row
+// rounded up to whole waves, so that short rows (e.g. 128 nodes) launch no idle waves.
+int row_block_threads(int nx, int V);
+
 // Device address (per device, looked up once) and size of the library's static scratch
 // array, and the FP64 totals of lbm_current reduced through it into device out[4].
 hipError_t static_scratch(int device, double **ptr, size_t *bytes);

@@ -108,19 +108,19 @@ def two_buffer_step(g: Grid, src: dict) -> dict:
 
 
 def pull_phase_threads(g: Grid):
-    """(reads, writes) of every thread of the pull phase; writes as (location, q, node)."""
+    """(reads, writes) of every thread of the pull phase; writes as (location, q, node).
+    Rows of free-slip wall planes leave at once; in every other row the threads load and
+    collide, fluid nodes store, and with two nodes per thread (16-bit) pairs are stored
+    whole, obstacle nodes included (in waves of obstacles only, too)."""
     threads = []
     for z in range(g.nz):
         for y in range(g.ny):
+            if g.wall_y(y) or g.wall_z(z):
+                continue
             for xw in range(0, g.nx, WAVE * g.V):  # one wave
-                wave_nodes = [(x, y, z) for x in range(xw, min(g.nx, xw + WAVE * g.V))]
-                wave_fluid = any(g.fluid(*n) for n in wave_nodes)
                 for x0 in range(xw, min(g.nx, xw + WAVE * g.V), g.V):
                     tn = [(x0 + i, y, z) for i in range(g.V)]
                     pairs = g.V == 2 and g.solid_slot
-                    active = wave_fluid if pairs else any(g.fluid(*n) for n in tn)
-                    if not active:
-                        continue
                     reads, writes = [], []
                     for n in tn:
                         takes_part = pairs or g.fluid(*n)
@@ -196,17 +196,21 @@ CASES = [
     ("D3V19", (6, 5, 5), 0.2, 3, 5),
     ("D3V19", (5, 4, 3), 0.25, 0, 6),
     ("D3V19", (4, 6, 5), 0.2, 1, 7),
+    ("D2V9", (12, 9, 1), 0.2, 1, 8, (3, 4)),   # rows y = 3, 4 all obstacles: waves of obstacles only
+    ("D3V19", (6, 5, 5), 0.15, 2, 9, (2,)),    # a plane of obstacles at y = 2, beside z walls
 ]
 
 
 @pytest.mark.parametrize("solid_slot,V", [(False, 1), (True, 1), (True, 2)], ids=["own-slot", "solid-slot", "pairs"])
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-{c[1][0]}x{c[1][1]}x{c[1][2]}-slip{c[3]}" for c in CASES])
 def test_inplace_phases_race_free_and_equal_to_two_buffers(case, solid_slot, V):
-    lattice, (nx, ny, nz), phi, slip, seed = case
+    lattice, (nx, ny, nz), phi, slip, seed = case[:5]
     if V == 2 and (lattice != "D2V9" or nx % 2):
         pytest.skip("two nodes per thread: 16-bit D2V9 rows of even length")
     rng = np.random.default_rng(seed)
     obst = (rng.random(nx * ny * nz) < phi).astype(np.uint8)
+    for yr in (case[5] if len(case) > 5 else ()):
+        obst.reshape(nz, ny, nx)[:, yr, :] = 1
     g = Grid(lattice, nx, ny, nz, obst, slip, solid_slot, V)
     # an even-layout state: a value at every location any pull reads
     s0 = {}
