@@ -481,10 +481,10 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
         lk[0] = *at32(static_cast<const LT *>(a.links), (unsigned)t.own);
         solid = (lk[0] & LinkMask<LAT>::solid) != 0;
     }
-    if (t.valid && solid) {
-#pragma unroll
-        for (int q = 0; q < L::Q; ++q) *at32(a.lam_out + slot_off(q, g.stride), (unsigned)t.own) = 0.f;
-    } else if (t.valid) {
+    // Solid nodes compute like fluid ones (their reads stay in bounds, and a solid node's
+    // link mask has no link bits) and then store zeros and contribute nothing: no lane waits
+    // for its link mask before its state and lambda loads issue.
+    if (t.valid) {
         float d[1][L::Q], gb[L::Q];
         gather_tile<LAT, ST, MASK, 1>(g, static_cast<const T *>(a.state), p.inv_scale, t, lk, d);
         adjoint_pull<LAT, MASK>(g, t, a.lam_in, lk[0], gb);
@@ -588,13 +588,15 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
             constexpr int q = decltype(qc)::value;
             float out = __builtin_fmaf(one_om, one_s * gb[q], base + edot<LAT, q>(Vs));
             if (SOFT) out = __builtin_fmaf(s, gb[L::opp[q]], out);
-            __builtin_nontemporal_store(out, at32(a.lam_out + slot_off(q, g.stride), (unsigned)t.own));
+            __builtin_nontemporal_store(solid ? 0.f : out, at32(a.lam_out + slot_off(q, g.stride), (unsigned)t.own));
         });
-        if (SOFT && a.grad_s) *at32(a.grad_s, (unsigned)t.own) = gs_prev + ds;
+        if (SOFT && a.grad_s && !solid) *at32(a.grad_s, (unsigned)t.own) = gs_prev + ds;
         acc[0] = (double)m.rho * (double)dE[0];
         acc[1] = (double)m.rho * (double)dE[1];
         acc[2] = (double)m.rho * (double)dE[2];
         acc[3] = (double)(om * om) * (double)dtau;
+        if (solid)
+            for (int c = 0; c < 4; ++c) acc[c] = 0.0;
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = wave_sum_last_lane(acc[c]);
@@ -645,10 +647,10 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_shift(AdjointArgs a)
         lk[0] = *at32(static_cast<const LT *>(a.links), (unsigned)t.own);
         solid = (lk[0] & LinkMask<LAT>::solid) != 0;
     }
-    if (t.valid && solid) {
-#pragma unroll
-        for (int q = 0; q < L::Q; ++q) *at32(a.lam_out + slot_off(q, g.stride), (unsigned)t.own) = 0.f;
-    } else if (t.valid) {
+    // Solid nodes compute like fluid ones (their reads stay in bounds, and a solid node's
+    // link mask has no link bits) and then store zeros and contribute nothing: no lane waits
+    // for its link mask before its state and lambda loads issue.
+    if (t.valid) {
         float d[1][L::Q], gb[L::Q];
         gather_tile<LAT, ST, MASK, 1>(g, static_cast<const T *>(a.state), p.inv_scale, t, lk, d);
         adjoint_pull<LAT, MASK>(g, t, a.lam_in, lk[0], gb);
@@ -731,9 +733,9 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_shift(AdjointArgs a)
             constexpr int q = decltype(qc)::value;
             float out = __builtin_fmaf(one_om, one_s * gb[q], base + edot<LAT, q>(H));
             if (SOFT) out = __builtin_fmaf(s, gb[L::opp[q]], out);
-            __builtin_nontemporal_store(out, at32(a.lam_out + slot_off(q, g.stride), (unsigned)t.own));
+            __builtin_nontemporal_store(solid ? 0.f : out, at32(a.lam_out + slot_off(q, g.stride), (unsigned)t.own));
         });
-        if (SOFT && a.grad_s) *at32(a.grad_s, (unsigned)t.own) = gs_prev + ds;
+        if (SOFT && a.grad_s && !solid) *at32(a.grad_s, (unsigned)t.own) = gs_prev + ds;
         const float rtc = m.rho * tau * p.cs;
         acc[0] = (double)(rtc * G[0]);
         acc[1] = (double)(rtc * G[1]);
@@ -742,6 +744,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_shift(AdjointArgs a)
 #pragma unroll
         for (int i = 0; i < 3; ++i) Gt = __builtin_fmaf(G[i], m.rho * p.cs * p.E[i] + jxB[i], Gt);
         acc[3] = (double)(om * om) * (double)dtau + (double)Gt;
+        if (solid)
+            for (int c = 0; c < 4; ++c) acc[c] = 0.0;
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = wave_sum_last_lane(acc[c]);
