@@ -1,21 +1,19 @@
 """The stopping rule of the Ohm's-law runs (Sec. 9.4), GPU through the C ABI: the average
-over fluid nodes with non-zero speed of | |u_new| - |u_old| | / |u_new| between
-consecutive steps (lbm_speed_change), and stepping until it falls below 1e-7
-(Simulation.run_until_steady).
+over fluid nodes with non-zero speed of | |u_new| - |u_old| | / |u_new| (lbm_speed_change),
+and stepping until its per-step value falls below 1e-7 (Simulation.run_until_steady).
 
 * The measure against numpy on the fields of two consecutive steps (2D and 3D grids with
   obstacles, the D1V7 thermal model).
 * The paper's 2D (512 x 256, 64 disks, slip y) and 3D (128^3, 450 balls, slip y and z)
-  Ohm samples with the velocity shift, tau = 0.9, run to the rule at E = 1e-7 and 2e-7:
-  both meet it, and the mean velocity over fluid nodes is linear in E (Ohm's law): 3D to
-  1e-4 (1e-6 measured), 2D to 1e-3 (2.7e-4 measured: the open 2D sample, porosity 0.986,
-  carries larger velocities, and the equilibrium's quadratic terms give relative
-  corrections of the order of u).
-  The threshold is 1e-6, not the paper's 1e-7: with FP32 storage the per-step change of
-  the steady flow has a rounding floor of 3-5e-7 (measured on the 2D sample: it passes
-  1.0e-7 near step 50000 while the flow still settles, then rises to that floor). The
-  dynamics are linear in E and the measure is relative, so both fields stop at the same
-  step and the linearity does not depend on how far the runs are from steady.
+  Ohm samples with the velocity shift, tau = 0.9, run to the paper's threshold 1e-7 at
+  E = 1e-7 and 2e-7: both meet it, and the mean velocity over fluid nodes is linear in E
+  (Ohm's law): 3D to 1e-4, 2D to 1e-3 (the open 2D sample, porosity 0.986, carries larger
+  velocities, and the equilibrium's quadratic terms give relative corrections of the order
+  of u). The per-step change is measured across 100 steps and divided by 100: with FP32
+  storage every node's speed jitters by about an ulp from step to step, a floor of 3-5e-7
+  on the change between two consecutive steps of the 2D sample (it passes 1e-7 near step
+  50000 and then rises to that floor), which the difference across 100 steps divides by
+  100 while the smooth settling of the flow keeps its per-step value.
 """
 import numpy as np
 import pytest
@@ -72,7 +70,7 @@ def test_ohm_samples_to_the_stopping_rule(name, builder, every, max_steps, lin):
         sim = lbm.Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=(E, 0, 0), mask=wl.mask,
                              forcing=wl.forcing, slip=wl.slip)
         sim.init(wl.rho)
-        steps, change = sim.run_until_steady(1e-6, every, max_steps)
+        steps, change = sim.run_until_steady(1e-7, every, max_steps, span=100)
         _, u = sim.moments()
         ux = u.cpu().numpy().reshape(sim.D, -1)[0]
         fluid = ux != 0
@@ -82,6 +80,6 @@ def test_ohm_samples_to_the_stopping_rule(name, builder, every, max_steps, lin):
         sim.close()
         print(f"{name} E={E:.0e}: steady after {steps} steps (change {change:.2e}), <u_x> = {mean_ux:.6e}, "
               f"<u_x>/E = {mean_ux / E:.6f}, fluid fraction {np.mean(solid == 0):.4f}")
-        assert change < 1e-6 and fluid.any()
+        assert change < 1e-7 and fluid.any()
     (E1, _, _, u1), (E2, _, _, u2) = res
     assert abs((u2 / E2) / (u1 / E1) - 1) < lin
