@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_pull(StepArgs a, int ntx, Fa
     using T = typename Codec<ST>::T;
     using LT = typename LinkMask<LAT>::T;
     if constexpr (MASK && !SLIP) a.g.slip = 0;  // no free-slip planes: reflections compiled out
-    const int bid = a.remap ? xcd_remap((int)blockIdx.x, nblocks) : (int)blockIdx.x;
+    const int bid = block_order((int)blockIdx.x, nblocks, a.remap);
     const Tile t = tile_of<V>(a.g, bid, ntx, div_ntx);
     if (!t.valid) return;
     // Rows of free-slip wall planes are solid as a whole: their blocks leave at once (a
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_local(StepArgs a, int ntx, F
     using T = typename Codec<ST>::T;
     using LT = typename LinkMask<LAT>::T;
     if constexpr (MASK && !SLIP) a.g.slip = 0;
-    const int bid = a.remap ? xcd_remap((int)blockIdx.x, nblocks) : (int)blockIdx.x;
+    const int bid = block_order((int)blockIdx.x, nblocks, a.remap);
     const Tile t = tile_of<V>(a.g, bid, ntx, div_ntx);
     if (!t.valid) return;
     // solid nodes load and collide too (their own slots, in bounds) and store nothing:
@@ -227,11 +227,13 @@ hipError_t aa_v(int force, int phase, const StepArgs &a, hipStream_t st)
     const int nblocks = ntx * a.g.ny * a.g.nz;
     const FastDiv div_ntx = make_fastdiv(ntx);
     const dim3 grid(nblocks), block(row_block_threads(a.g.nx, V));
+    StepArgs b = a;
+    b.remap = remap_code(a.remap, ntx);
 #define LBM_AA_SL(M, S, F, SL)                                                                                     \
     if (phase == 0)                                                                                               \
-        hipLaunchKernelGGL((k_step_aa_pull<LAT, ST, M, S, F, V, SL>), grid, block, 0, st, a, ntx, div_ntx, nblocks); \
+        hipLaunchKernelGGL((k_step_aa_pull<LAT, ST, M, S, F, V, SL>), grid, block, 0, st, b, ntx, div_ntx, nblocks); \
     else                                                                                                          \
-        hipLaunchKernelGGL((k_step_aa_local<LAT, ST, M, S, F, V, SL>), grid, block, 0, st, a, ntx, div_ntx, nblocks)
+        hipLaunchKernelGGL((k_step_aa_local<LAT, ST, M, S, F, V, SL>), grid, block, 0, st, b, ntx, div_ntx, nblocks)
 #define LBM_AA(M, S, F)           \
     do {                          \
         if (M && a.g.slip) {      \

@@ -201,6 +201,25 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb)
     return xcd * per + min(xcd, rem) + k;
 }
 
+// Block order of the node kernels (the hardware deals blocks round-robin to the 8 XCDs):
+//   remap 0: the hardware order;
+//   remap 1: each XCD a contiguous slab of the grid (xcd_remap);
+//   remap c >= 2: chunks of 2^(c - 2) consecutive tiles (a whole row of tiles) dealt
+//   round-robin to the XCDs, so that the tiles of a row, which share the cache lines at
+//   their x edges, run on one XCD (one L2) while the 8 XCDs still work on neighbouring
+//   rows; a tail of fewer than 8 chunks keeps the hardware order.
+__device__ __forceinline__ int block_order(int bid, int nb, int remap)
+{
+    if (remap == 1) return xcd_remap(bid, nb);
+    if (remap >= 2) {
+        const int sh = remap - 2, group = 8 << sh;
+        if (bid >= nb - nb % group) return bid;
+        const int xcd = bid & 7, k = bid >> 3;
+        return ((((k >> sh) << 3) + xcd) << sh) + (k & ((1 << sh) - 1));
+    }
+    return bid;
+}
+
 __device__ __forceinline__ int wrapm(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 __device__ __forceinline__ int wrapp(int i, int n) { return i == n - 1 ? 0 : i + 1; }
 

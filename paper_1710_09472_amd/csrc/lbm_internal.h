@@ -218,6 +218,7 @@ hipError_t launch_reduce_final(const double *partials, int nparts, int ncomp, do
                                int accumulate, hipStream_t st, double *stage);
 int step_vector_width(int lattice, int storage, int nx);
 int use_xcd_remap(int lattice, bool mask, bool soft);
+int remap_code(int remap, int ntx);
 // shift: the adjoint of the velocity-shift forcing (k_adjoint_shift), else of the source
 hipError_t launch_adjoint(int lattice, int storage, bool mag, bool shift, const AdjointArgs &a, hipStream_t st);
 // In-place step (lbm_aa.hip), a.src == a.dst: phase 0 takes the state from the two-buffer

@@ -43,12 +43,25 @@ int step_vector_width(int lattice, int storage, int nx)
 
 // XCD-contiguous block order (measured on MI355X): it pays off where the reads of a node
 // span several rows of solids or planes (D3V19, masks, porosity fields) and costs ~8 %
-// on the plain D2V9 grid, which keeps the hardware order. LBM_XCD_REMAP=0|1 overrides.
+// on the plain D2V9 grid, which keeps the hardware order. 2 asks for whole rows of tiles
+// per XCD, dealt round-robin (block_order; remap_code turns it into the kernel's code).
+// LBM_XCD_REMAP=0|1|2 overrides.
 int use_xcd_remap(int lattice, bool mask, bool soft)
 {
     static const int forced = env_int("LBM_XCD_REMAP", -1);
-    if (forced == 0 || forced == 1) return forced;
+    if (forced == 0 || forced == 1 || forced == 2) return forced;
     return (lattice == LBM_D3V19 || mask || soft) ? 1 : 0;
+}
+
+// The block_order code of a launch with ntx tiles per row: 2 + log2(ntx) for whole rows
+// per XCD where ntx is a power of two, the hardware order where it is not.
+int remap_code(int remap, int ntx)
+{
+    if (remap != 2) return remap;
+    if (ntx < 1 || (ntx & (ntx - 1))) return 0;
+    int sh = 0;
+    while ((1 << sh) < ntx) ++sh;
+    return 2 + sh;
 }
 
 // One block per row where the row fits in a block: the row's waves only (tile_of then
@@ -77,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, int ntx, FastDiv di
     // loads issued before the link masks arrive); the kernels without solids keep the
     // runtime test, whose code measured 3 % faster on the 4096^2 FP32 grid
     if constexpr (MASK && !SLIP) a.g.slip = 0;
-    const int bid = a.remap ? xcd_remap((int)blockIdx.x, nblocks) : (int)blockIdx.x;
+    const int bid = block_order((int)blockIdx.x, nblocks, a.remap);
     const Tile t = tile_of<V>(a.g, bid, ntx, div_ntx);
     if (!t.valid) return;  // beyond the row (rows shorter than a block): no work
     LT lk[V];
@@ -456,7 +469,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(AdjointArgs a)
     using LT = typename LinkMask<LAT>::T;
     const Geometry &g = a.g;
     const Physics &p = a.ph;
-    const int bid = a.remap ? xcd_remap((int)blockIdx.x, g.nblocks) : (int)blockIdx.x;
+    const int bid = block_order((int)blockIdx.x, g.nblocks, a.remap);
     const Tile t = tile_of(g, bid);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     // One partial per wave, written by its last lane. The accumulated value is read first
@@ -626,7 +639,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_shift(AdjointArgs a)
     using LT = typename LinkMask<LAT>::T;
     const Geometry &g = a.g;
     const Physics &p = a.ph;
-    const int bid = a.remap ? xcd_remap((int)blockIdx.x, g.nblocks) : (int)blockIdx.x;
+    const int bid = block_order((int)blockIdx.x, g.nblocks, a.remap);
     const Tile t = tile_of(g, bid);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const bool last_lane = (threadIdx.x & 63) == 63;
@@ -781,12 +794,14 @@ hipError_t step_v(int force, const StepArgs &a, hipStream_t st)
     const int nblocks = ntx * a.g.ny * a.g.nz;
     const FastDiv div_ntx = make_fastdiv(ntx);
     const dim3 grid(nblocks), block(row_block_threads(a.g.nx, V));
+    StepArgs b = a;
+    b.remap = remap_code(a.remap, ntx);
 #define LBM_STEP(M, S, F)                                                                                      \
     do {                                                                                                       \
-        if (M && a.g.slip)                                                                                     \
-            hipLaunchKernelGGL((k_step<LAT, ST, M, S, F, V, M>), grid, block, 0, st, a, ntx, div_ntx, nblocks); \
+        if (M && b.g.slip)                                                                                     \
+            hipLaunchKernelGGL((k_step<LAT, ST, M, S, F, V, M>), grid, block, 0, st, b, ntx, div_ntx, nblocks); \
         else                                                                                                   \
-            hipLaunchKernelGGL((k_step<LAT, ST, M, S, F, V, false>), grid, block, 0, st, a, ntx, div_ntx,      \
+            hipLaunchKernelGGL((k_step<LAT, ST, M, S, F, V, false>), grid, block, 0, st, b, ntx, div_ntx,      \
                                nblocks);                                                                       \
     } while (0)
 #define LBM_STEP_F(M, S)   \
@@ -821,12 +836,14 @@ hipError_t adjoint_lat_st(bool mag, bool shift, const AdjointArgs &a, hipStream_
 {
     const bool mask = a.links != nullptr, soft = a.g.s != nullptr;
     const dim3 grid(a.g.nblocks), block(row_block_threads(a.g.nx, 1));
+    AdjointArgs b = a;
+    b.remap = remap_code(a.remap, a.g.ntx);
 #define LBM_ADJ(M, S, B)                                                                  \
     do {                                                                                  \
         if (shift)                                                                        \
-            hipLaunchKernelGGL((k_adjoint_shift<LAT, ST, M, S, B>), grid, block, 0, st, a); \
+            hipLaunchKernelGGL((k_adjoint_shift<LAT, ST, M, S, B>), grid, block, 0, st, b); \
         else                                                                              \
-            hipLaunchKernelGGL((k_adjoint<LAT, ST, M, S, B>), grid, block, 0, st, a);       \
+            hipLaunchKernelGGL((k_adjoint<LAT, ST, M, S, B>), grid, block, 0, st, b);       \
     } while (0)
     if (mask) {
         if (soft) {
