@@ -244,9 +244,23 @@ def adjoint_pipeline():
     t2 = time.perf_counter()
     sim.close()
     fwd, bwd = (t1 - t0) / wl.steps, (t2 - t1) / wl.steps
-    return {"workload": "soft_porous_3d: D3V19 128^3, mean s 0.2, E_x 1e-6, tau 0.75, 600 steps, K=50",
-            "forward_ms_per_step": round(fwd * 1e3, 5), "reverse_ms_per_step": round(bwd * 1e3, 5),
-            "ratio_to_forward": round(bwd / fwd, 3), "dJ_dEx": float(gE[0]), "dJ_dtau": float(gT)}
+    out = {"workload": "soft_porous_3d: D3V19 128^3, mean s 0.2, E_x 1e-6, tau 0.75, 600 steps, K=50",
+           "forward_ms_per_step": round(fwd * 1e3, 5), "reverse_ms_per_step": round(bwd * 1e3, 5),
+           "ratio_to_forward": round(bwd / fwd, 3), "dJ_dEx": float(gE[0]), "dJ_dtau": float(gT)}
+    # the stated error: against the FP64 oracle's central differences at the same size and
+    # steps, stored in the repository (tests/golden/soft_porous_fd.json)
+    gold_path = ROOT / "tests" / "golden" / "soft_porous_fd.json"
+    if gold_path.exists():
+        import numpy as np
+
+        gold = json.loads(gold_path.read_text())
+        v = np.random.default_rng(gold["h"]["direction_seed"]).standard_normal(wl.N)
+        gS = float(gs.double().cpu().numpy() @ v)
+        out["err_vs_oracle_fd"] = {"dJ_dEx": float(f"{abs(out['dJ_dEx'] / gold['dJ_dEx'] - 1):.3g}"),
+                                   "dJ_dtau": float(f"{abs(out['dJ_dtau'] / gold['dJ_dtau'] - 1):.3g}"),
+                                   "dJ_ds_along_v": float(f"{abs(gS / gold['dJ_ds_dot_v'] - 1):.3g}"),
+                                   "h": 1e-4}
+    return out
 
 
 def kernel_code_hash(thermal: bool = False) -> str:
