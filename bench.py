@@ -264,13 +264,14 @@ def adjoint_pipeline():
 
 
 def kernel_code_hash(thermal: bool = False) -> str:
-    """sha256 of a step kernel's sources (the device header and the kernel file: the
+    """sha256 of a step kernel's sources (the device header and the kernel files: the
     isothermal step's or the thermal step's) without // comments and blank lines: it
     changes with the code, not with its comments."""
     import hashlib
 
     lines = []
-    for name in ("lbm_device.h", "lbm_thermal.hip" if thermal else "lbm_kernels.hip"):
+    names = ("lbm_thermal.hip",) if thermal else ("lbm_step_kernels.h", "lbm_kernels.hip")
+    for name in ("lbm_device.h",) + names:
         for line in (ROOT / "paper_1710_09472_amd" / "csrc" / name).read_text().splitlines():
             line = re.sub(r"//.*$", "", line).rstrip()
             if line.strip():
@@ -455,6 +456,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="throughput_2d", choices=sorted(WORKLOAD_DESC))
     ap.add_argument("--storage", default="f32", choices=("f32", "f16", "bf16"))
+    ap.add_argument("--rounding", default="nearest", choices=("nearest", "stochastic"),
+                    help="rounding of the stored 16-bit values")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the main step")
     ap.add_argument("--inplace", action="store_true",
@@ -493,7 +496,7 @@ def main():
     k16 = F16_SCALE[args.workload] if st == "f16" else 0
     sim = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E, B=wl.B, storage=st,
                      dev_scale_log2=k16, mask=wl.mask, s=wl.s, forcing=wl.forcing, slip=wl.slip,
-                     inplace=args.inplace, theta=wl.theta, mu=wl.mu)
+                     inplace=args.inplace, theta=wl.theta, mu=wl.mu, rounding=args.rounding)
     if thermal:
         sim.init(wl.rho, wl.u, wl.thetabar)
     else:
@@ -503,7 +506,7 @@ def main():
     mlups = N * args.steps / wall / 1e6
     alg = algorithmic_bytes(wl, sim.Q, elem)
     achieved = alg / t_launch / 1e9
-    traffic = None if args.inplace else traffic_from_profile(
+    traffic = None if (args.inplace or args.rounding != "nearest") else traffic_from_profile(
         f"{'k_thermal_step' if thermal else 'k_step'}_{wl.lattice}_{st}_{args.workload}")
     tot = sim.current()
     sim.close()
@@ -512,15 +515,17 @@ def main():
     default = args.workload == "throughput_2d" and st == "f32"
     extras = {}
     if default and not args.no_extras:
-        for s16s, k in (("f16", F16_SCALE["throughput_2d"]), ("bf16", 0)):
-            s16 = Simulation(wl.lattice, wl.nx, wl.ny, 1, tau=wl.tau, storage=s16s, dev_scale_log2=k)
+        for s16s, k, rnd in (("f16", F16_SCALE["throughput_2d"], "nearest"), ("bf16", 0, "nearest"),
+                             ("f16", F16_SCALE["throughput_2d"], "stochastic"), ("bf16", 0, "stochastic")):
+            s16 = Simulation(wl.lattice, wl.nx, wl.ny, 1, tau=wl.tau, storage=s16s, dev_scale_log2=k, rounding=rnd)
             s16.init(wl.rho)
             w16, e16 = timed_steps(s16, args.steps, args.warmup)
             t16 = e16 / args.steps
-            extras[s16s] = {"MLUPS": round(N * args.steps / w16 / 1e6, 1),
-                            "ms_per_step": round(w16 / args.steps * 1e3, 5),
-                            "achieved_GBs": round(bytes_per_node(s16.Q, 2) * N / t16 / 1e9, 1),
-                            "dev_scale_log2": k}
+            extras[s16s if rnd == "nearest" else s16s + "_stochastic_rounding"] = {
+                "MLUPS": round(N * args.steps / w16 / 1e6, 1),
+                "ms_per_step": round(w16 / args.steps * 1e3, 5),
+                "achieved_GBs": round(bytes_per_node(s16.Q, 2) * N / t16 / 1e9, 1),
+                "dev_scale_log2": k}
             s16.close()
         extras["adjoint"] = {}
         for key, forcing in (("step_only_4096sq", "source"), ("step_only_4096sq_shift", "shift")):
@@ -542,9 +547,10 @@ def main():
               "k_step_aa_pull+k_step_aa_local" if args.inplace else "k_step") + \
         f"<{wl.lattice},{st.upper()}" + (",mask" if wl.mask is not None else "") + \
         (",slip" if wl.slip else "") + (",soft" if wl.s is not None else "") + \
-        (",shift" if wl.forcing == "shift" else "") + ">"
+        (",shift" if wl.forcing == "shift" else "") + (",stochastic" if args.rounding == "stochastic" else "") + ">"
     desc = WORKLOAD_DESC[args.workload] + {"f32": ", FP32", "f16": f", FP16 x 2^{k16}", "bf16": ", BF16"}[st] + \
-        " deviation storage" + (", in-place step (one state buffer)" if args.inplace else "")
+        " deviation storage" + (", stochastic rounding" if args.rounding == "stochastic" else "") + \
+        (", in-place step (one state buffer)" if args.inplace else "")
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -568,7 +574,8 @@ def main():
     if solid is not None:
         out["fluid_MLUPS"] = round(int((solid == 0).sum()) * args.steps / wall / 1e6, 1)
     if default:
-        out["storage16"] = extras.get("f16") and {"f16": extras["f16"], "bf16": extras["bf16"]}
+        out["storage16"] = extras.get("f16") and {key: v for key, v in extras.items()
+                                                  if key.startswith(("f16", "bf16"))}
         out["adjoint"] = extras.get("adjoint")
         out["inplace"] = extras.get("inplace")
         out["thermal"] = extras.get("thermal")

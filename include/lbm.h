@@ -56,9 +56,21 @@ enum { LBM_FERMI_DIRAC = 0, LBM_BOSE_EINSTEIN = 1, LBM_HERMITE = 2 };
 /* Population storage. All arithmetic is FP32; storage holds deviations
  * d_a = f_a - what_a rho0 from the rest equilibrium (what_a = w_a / I_0):
  *   LBM_F32  : float d_a
- *   LBM_F16  : IEEE half of d_a * 2^dev_scale_log2, round to nearest even
- *   LBM_BF16 : bfloat16 of d_a, round to nearest even                          */
+ *   LBM_F16  : IEEE half of d_a * 2^dev_scale_log2
+ *   LBM_BF16 : bfloat16 of d_a
+ * 16-bit values are rounded to nearest even, or stochastically (lbm_params.rounding). */
 enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 };
+
+/* Rounding of the 16-bit stored values written by the time steps (not in the paper):
+ *   LBM_ROUND_NEAREST    : round to nearest even (the default);
+ *   LBM_ROUND_STOCHASTIC : stochastic rounding (gfx950 v_cvt_sr_*): up or down with
+ *                          probabilities given by the distance to the two neighbours, so
+ *                          that a change smaller than half a unit in the last place is kept
+ *                          on average instead of lost at every step. The random bits are a
+ *                          hash of (node, population, step index): runs repeat bit for bit,
+ *                          and the in-place and two-buffer steps agree bit for bit.
+ * Initial states (lbm_init) are always rounded to nearest. LBM_F16 and LBM_BF16 only. */
+enum { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 };
 
 enum {
     LBM_OK = 0,
@@ -99,6 +111,7 @@ typedef struct {
     int order;          /* D1V7 only: truncation order K of the equilibrium expansion, 3 (the
                          * momentum equation, Sec. 6) or 4 (also the energy equation); 0 = 4.
                          * Must be 0 for D2V9/D3V19 (second order, Sec. 9.1). */
+    int rounding;       /* LBM_ROUND_NEAREST or LBM_ROUND_STOCHASTIC (16-bit D2V9/D3V19 only) */
 } lbm_params;
 
 /* Constants the library derives from the parameters (host FP64), exposed for
@@ -203,9 +216,17 @@ int lbm_step(lbm_t h, int nsteps);
 /* One step of the discrete BGK update of Sec. 9.1 (as lbm_step) from the state in `src`
  * into `dst` (device state buffers of state_bytes,
  * distinct, neither need be the handle's own; two-buffer layout, as lbm_get_state
- * writes it); the handle's state is not touched. Used to recompute trajectories for
+ * writes it); the handle's state is not touched, its step index advances by one (it
+ * selects the random bits of stochastic rounding). Used to recompute trajectories for
  * the adjoint. Async. */
 int lbm_step_from(lbm_t h, const void *src, void *dst);
+
+/* Not in the paper. The index of the handle's next time step (steps since lbm_init, which
+ * sets it to 0, as lbm_set_state does); lbm_step and lbm_step_from advance it by one per
+ * step. With LBM_ROUND_STOCHASTIC the random bits of step t are a function of t, so a
+ * caller that recomputes steps (checkpointed adjoints, restarts) sets the index of the
+ * first one here to repeat the run bit for bit; it has no effect otherwise. Host only. */
+int lbm_set_step_index(lbm_t h, unsigned long long t);
 
 /* Macroscopic fields of eq. (mac-fields-model-sec-eq), Sec. 9.1, of the current state
  * (pre-collision): rho = sum_a f_a (device float[N]) and u = sum_a f_a xi_a / rho (device

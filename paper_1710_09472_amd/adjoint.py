@@ -79,6 +79,7 @@ def adjoint_gradients(pb: Problem, sim: Simulation, cps):
         t0 = i * K
         n = min(K, pb.steps - t0)
         seg_bufs[0].copy_(cps[i])
+        sim.set_step_index(t0)  # the recomputed steps repeat the forward run's bits
         for k in range(1, n):
             sim.step_from(seg_bufs[k - 1], seg_bufs[k])
         for k in range(n - 1, -1, -1):

@@ -22,7 +22,7 @@ CSRC = PKG / "csrc"
 INCLUDE = ROOT / "include"
 BUILD = PKG / "_build"
 LIB = PKG / "liblbm_hip.so"
-SOURCES = ["lbm_kernels.hip", "lbm_aa.hip", "lbm_thermal.hip", "lbm_density.hip", "lbm_capi.cpp", "lbm_consts.cpp"]
+SOURCES = ["lbm_kernels.hip", "lbm_aa.hip", "lbm_step_sr.hip", "lbm_aa_sr.hip", "lbm_thermal.hip", "lbm_density.hip", "lbm_capi.cpp", "lbm_consts.cpp"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 

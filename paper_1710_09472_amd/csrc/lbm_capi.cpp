@@ -39,6 +39,7 @@ struct lbm_s {
     int cur = 0;
     bool aa = false;  // one state buffer: in-place steps (AA pattern)
     int parity = 0;   // in-place steps since the last even layout, mod 2
+    unsigned long long t = 0;  // index of the next step (selects the stochastic-rounding bits)
     unsigned char *work = nullptr;
     hipStream_t stream = nullptr;
     Geometry g{};
@@ -129,6 +130,18 @@ WorkLayout work_layout(int nblocks, int stride)
 }
 
 // Validation shared by create and the size query. Writes the message through fail().
+// The key of step t for the random bits of stochastic rounding: the SplitMix64 output
+// function (Steele, Lea and Flood, OOPSLA 2014) of t, upper half. The kernels hash it
+// with the node index (sr_node).
+uint32_t sr_step_key(unsigned long long t)
+{
+    uint64_t z = (uint64_t)t + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (uint32_t)(z >> 32);
+}
+
 int validate(const lbm_params *p, lbm_t h, Sizes *sz)
 {
     if (!p) return fail(h, LBM_EINVAL, "null params");
@@ -172,6 +185,10 @@ int validate(const lbm_params *p, lbm_t h, Sizes *sz)
     if (D == 2 && (p->slip & LBM_SLIP_Z)) return fail(h, LBM_EINVAL, "2D lattice: no z walls");
     if (((p->slip & LBM_SLIP_Y) && p->ny < 3) || ((p->slip & LBM_SLIP_Z) && p->nz < 3))
         return fail(h, LBM_EINVAL, "a free-slip axis needs at least 3 planes (2 walls and fluid)");
+    if (p->rounding != LBM_ROUND_NEAREST && p->rounding != LBM_ROUND_STOCHASTIC)
+        return fail(h, LBM_EINVAL, "unknown rounding %d", p->rounding);
+    if (p->rounding == LBM_ROUND_STOCHASTIC && (p->storage == LBM_F32 || p->lattice == LBM_D1V7))
+        return fail(h, LBM_EINVAL, "stochastic rounding: FP16 or BF16 storage of D2V9/D3V19 only");
     if (sz) {
         sz->N = (int)N;
         sz->stride = (int)stride;
@@ -551,6 +568,7 @@ int lbm_init_thermal(lbm_t h, const double *rho, const double *u, const double *
     if (e != hipSuccess) return hip_fail(h, e, "thermal init kernel launch");
     h->initialized = true;
     h->parity = 0;
+    h->t = 0;
     return LBM_OK;
 }
 
@@ -570,6 +588,7 @@ int lbm_init(lbm_t h, const double *rho, const double *u)
     if (e != hipSuccess) return hip_fail(h, e, "init kernel launch");
     h->initialized = true;
     h->parity = 0;
+    h->t = 0;
     return LBM_OK;
 }
 
@@ -583,6 +602,7 @@ int lbm_step(lbm_t h, int nsteps)
     a.ph = h->ph;
     a.links = links_of(h);
     a.remap = use_xcd_remap(h->p.lattice, has_solids(h), h->s != nullptr);
+    a.sr = h->p.rounding == LBM_ROUND_STOCHASTIC ? 1 : 0;
     if (h->thermal && h->aa) {
         ThermalArgs ta = thermal_args(h);
         ta.src = ta.dst = h->buf[0];
@@ -590,6 +610,7 @@ int lbm_step(lbm_t h, int nsteps)
             const hipError_t e = launch_thermal(5 + h->parity, h->p.storage, ta, 0, h->stream);
             if (e != hipSuccess) return hip_fail(h, e, "in-place thermal step kernel launch");
             h->parity ^= 1;
+            ++h->t;
         }
         return LBM_OK;
     }
@@ -601,6 +622,7 @@ int lbm_step(lbm_t h, int nsteps)
             const hipError_t e = launch_thermal(0, h->p.storage, ta, 0, h->stream);
             if (e != hipSuccess) return hip_fail(h, e, "thermal step kernel launch");
             h->cur ^= 1;
+            ++h->t;
         }
         return LBM_OK;
     }
@@ -608,18 +630,22 @@ int lbm_step(lbm_t h, int nsteps)
     if (h->aa) {
         a.src = a.dst = h->buf[0];
         for (int t = 0; t < nsteps; ++t) {
+            a.sr_key = sr_step_key(h->t);
             const hipError_t e = launch_step_aa(h->p.lattice, h->p.storage, force, h->parity, a, h->stream);
             if (e != hipSuccess) return hip_fail(h, e, "in-place step kernel launch");
             h->parity ^= 1;
+            ++h->t;
         }
         return LBM_OK;
     }
     for (int t = 0; t < nsteps; ++t) {
         a.src = h->buf[h->cur];
         a.dst = h->buf[h->cur ^ 1];
+        a.sr_key = sr_step_key(h->t);
         const hipError_t e = launch_step(h->p.lattice, h->p.storage, force, a, h->stream);
         if (e != hipSuccess) return hip_fail(h, e, "step kernel launch");
         h->cur ^= 1;
+        ++h->t;
     }
     return LBM_OK;
 }
@@ -634,6 +660,7 @@ int lbm_step_from(lbm_t h, const void *src, void *dst)
         ta.dst = dst;
         const hipError_t e = launch_thermal(0, h->p.storage, ta, 0, h->stream);
         if (e != hipSuccess) return hip_fail(h, e, "thermal step kernel launch");
+        ++h->t;
         return LBM_OK;
     }
     StepArgs a{};
@@ -641,10 +668,13 @@ int lbm_step_from(lbm_t h, const void *src, void *dst)
     a.ph = h->ph;
     a.links = links_of(h);
     a.remap = use_xcd_remap(h->p.lattice, has_solids(h), h->s != nullptr);
+    a.sr = h->p.rounding == LBM_ROUND_STOCHASTIC ? 1 : 0;
+    a.sr_key = sr_step_key(h->t);
     a.src = src;
     a.dst = dst;
     const hipError_t e = launch_step(h->p.lattice, h->p.storage, force_level(h), a, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "step kernel launch");
+    ++h->t;
     return LBM_OK;
 }
 
@@ -857,6 +887,14 @@ int lbm_set_state(lbm_t h, const void *src)
     if (e != hipSuccess) return hip_fail(h, e, "state copy");
     h->initialized = true;
     h->parity = 0;
+    h->t = 0;
+    return LBM_OK;
+}
+
+int lbm_set_step_index(lbm_t h, unsigned long long t)
+{
+    if (!h) return fail(nullptr, LBM_EINVAL, "null handle");
+    h->t = t;
     return LBM_OK;
 }
 

@@ -14,7 +14,8 @@
 namespace lbm {
 
 // ---------------------------------------------------------------------------------
-// Storage codecs: deviation <-> stored value (round to nearest even).
+// Storage codecs: deviation <-> stored value (round to nearest even; stochastic
+// rounding for the 16-bit formats further down).
 // ---------------------------------------------------------------------------------
 template <int ST>
 struct Codec;
@@ -24,6 +25,7 @@ struct Codec<LBM_F32> {
     using T = float;
     static __device__ __forceinline__ float dec(T v, float) { return v; }
     static __device__ __forceinline__ T enc(float f, float) { return f; }
+    static __device__ __forceinline__ T enc_sr(float f, uint32_t) { return f; }
 };
 
 // Encoding rounds the FP32 value: the empty asm statement makes it opaque, so that the
@@ -42,6 +44,19 @@ struct Codec<LBM_F16> {
     // stored value = d * 2^k; the scale is a power of two, so scaling is exact
     static __device__ __forceinline__ float dec(T v, float inv_scale) { return (float)v * inv_scale; }
     static __device__ __forceinline__ T enc(float f, float scale) { return (T)opaque(f * scale); }
+    // stochastic rounding of a value already in stored units, random bits r
+    typedef _Float16 T2 __attribute__((ext_vector_type(2)));
+    static __device__ __forceinline__ T enc_sr(float f, uint32_t r)
+    {
+        return __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(T2, r), opaque(f), r, false)[0];
+    }
+    // two values into one register (a low, b high): the second conversion writes the high
+    // half in place, and the first one's register is that of its random word
+    static __device__ __forceinline__ T2 enc_sr2(float a, uint32_t ra, float b, uint32_t rb)
+    {
+        const T2 lo = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(T2, ra), opaque(a), ra, false);
+        return __builtin_amdgcn_cvt_sr_f16_f32(lo, opaque(b), rb, true);
+    }
 };
 
 template <>
@@ -49,7 +64,51 @@ struct Codec<LBM_BF16> {
     using T = __bf16;
     static __device__ __forceinline__ float dec(T v, float) { return (float)v; }
     static __device__ __forceinline__ T enc(float f, float) { return (T)opaque(f); }
+    typedef __bf16 T2 __attribute__((ext_vector_type(2)));
+    static __device__ __forceinline__ T enc_sr(float f, uint32_t r)
+    {
+        return __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(T2, r), opaque(f), r, false)[0];
+    }
+    static __device__ __forceinline__ T2 enc_sr2(float a, uint32_t ra, float b, uint32_t rb)
+    {
+        const T2 lo = __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(T2, ra), opaque(a), ra, false);
+        return __builtin_amdgcn_cvt_sr_bf16_f32(lo, opaque(b), rb, true);
+    }
 };
+
+// ---------------------------------------------------------------------------------
+// Stochastic rounding of the stored 16-bit values (optional; not in the paper). The
+// random bits for the value of population q that the step of key k writes for node n
+// are sr_bits(sr_node(n, k), q): one integer hash per node -- Wellons's "lowbias32"
+// mixer, a bijection of 32-bit words -- of the node index and the step's key, then a
+// Weyl increment per population (any fixed set of bits of the result is uniform over
+// the nodes). Each stored value carries the bits of its own (node, population), so the
+// same value gets the same bits wherever a step stores it (own slot, solid slot, the
+// layouts of the in-place step).
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t sr_node(uint32_t n, uint32_t key)
+{
+    uint32_t x = (n * 0x9E3779B9u) ^ key;
+    x ^= x >> 16;
+    x *= 0x7FEB352Du;
+    x ^= x >> 15;
+    x *= 0x846CA68Bu;
+    x ^= x >> 16;
+    return x;
+}
+
+__device__ __forceinline__ uint32_t sr_bits(uint32_t h, int q) { return h + (uint32_t)q * 0x9E3779B9u; }
+
+// The stored code of a value in stored units: round to nearest even, or stochastic with
+// the bits of (node hash h, population q).
+template <int ST, bool SR>
+__device__ __forceinline__ typename Codec<ST>::T enc_store(float f, uint32_t h, int q)
+{
+    if constexpr (SR)
+        return Codec<ST>::enc_sr(f, sr_bits(h, q));
+    else
+        return Codec<ST>::enc(f, 1.f);
+}
 
 // Where a bounced population is kept between steps (halfway bounce-back: the value
 // pulled into fluid x as population q, when x - e_q is solid, is f*_qbar(x)):
@@ -90,26 +149,55 @@ __device__ __forceinline__ void vload(const typename Codec<ST>::T *p, float inv_
     }
 }
 
+// V encoded values (V-wide store)
 template <int ST, int V>
-__device__ __forceinline__ void vstore(typename Codec<ST>::T *p, float scale, const float *f)
+__device__ __forceinline__ void vstore_codes(typename Codec<ST>::T *p, const typename Codec<ST>::T *c)
 {
     if constexpr (V == 1) {
-        const typename Codec<ST>::T v = Codec<ST>::enc(f[0], scale);
 #if LBM_NT_STORE
-        __builtin_nontemporal_store(v, p);
+        __builtin_nontemporal_store(c[0], p);
 #else
-        *p = v;
+        *p = c[0];
 #endif
     } else {
         using VT = typename VecT<ST, V>::type;
         VT v;
 #pragma unroll
-        for (int i = 0; i < V; ++i) v[i] = Codec<ST>::enc(f[i], scale);
+        for (int i = 0; i < V; ++i) v[i] = c[i];
 #if LBM_NT_STORE
         __builtin_nontemporal_store(v, reinterpret_cast<VT *>(p));
 #else
         *reinterpret_cast<VT *>(p) = v;
 #endif
+    }
+}
+
+template <int ST, int V>
+__device__ __forceinline__ void vstore(typename Codec<ST>::T *p, float scale, const float *f)
+{
+    typename Codec<ST>::T c[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) c[i] = Codec<ST>::enc(f[i], scale);
+    vstore_codes<ST, V>(p, c);
+}
+
+// Population q of V consecutive nodes with node hashes h (values in stored units).
+template <int ST, int V, bool SR>
+__device__ __forceinline__ void vstore_q(typename Codec<ST>::T *p, const float *f, const uint32_t *h, int q)
+{
+    if constexpr (SR && V == 2 && ST != LBM_F32) {
+        using VT = typename VecT<ST, 2>::type;
+        const VT v = Codec<ST>::enc_sr2(f[0], sr_bits(h[0], q), f[1], sr_bits(h[1], q));
+#if LBM_NT_STORE
+        __builtin_nontemporal_store(v, reinterpret_cast<VT *>(p));
+#else
+        *reinterpret_cast<VT *>(p) = v;
+#endif
+    } else {
+        typename Codec<ST>::T c[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) c[i] = enc_store<ST, SR>(f[i], SR ? h[i] : 0u, q);
+        vstore_codes<ST, V>(p, c);
     }
 }
 
@@ -648,9 +736,11 @@ __device__ __forceinline__ void collide(const Physics &p, const float *D, float 
 // (slot q of x), and with the solid-slot convention each bounced one where the next pull
 // reads it: where x - e_q is solid, the value pulled into x as population q is
 // f*_qbar(x), kept in slot q of that solid node.
-template <int LAT, int ST, bool MASK, int V>
+// With SR the codes are rounded stochastically with the node hashes h (sr_node).
+template <int LAT, int ST, bool MASK, int V, bool SR = false>
 __device__ __forceinline__ void store_tile(const Geometry &g, typename Codec<ST>::T *__restrict__ dst, const Tile &t,
-                                           const typename LinkMask<LAT>::T (&lk)[V], const float (&o)[V][Lat<LAT>::Q])
+                                           const typename LinkMask<LAT>::T (&lk)[V], const float (&o)[V][Lat<LAT>::Q],
+                                           const uint32_t *h = nullptr)
 {
     using L = Lat<LAT>;
     using T = typename Codec<ST>::T;
@@ -671,11 +761,11 @@ __device__ __forceinline__ void store_tile(const Geometry &g, typename Codec<ST>
             float f[V];
 #pragma unroll
             for (int i = 0; i < V; ++i) f[i] = o[i][q];
-            vstore<ST, V>(p, 1.f, f);
+            vstore_q<ST, V, SR>(p, f, h, q);
         } else {
 #pragma unroll
             for (int i = 0; i < V; ++i)
-                if (fluid[i]) *at32(p, (unsigned)i) = Codec<ST>::enc(o[i][q], 1.f);
+                if (fluid[i]) *at32(p, (unsigned)i) = enc_store<ST, SR>(o[i][q], SR ? h[i] : 0u, q);
         }
     }
     if (MASK && kSolidSlotBB<ST> && links) {
@@ -687,7 +777,8 @@ __device__ __forceinline__ void store_tile(const Geometry &g, typename Codec<ST>
 #pragma unroll
                 for (int i = 0; i < V; ++i)
                     if (fluid[i] && ((lk[i] >> q) & 1u))
-                        *at32(row, pull_x<LAT, q, V>(r, i)) = Codec<ST>::enc(o[i][L::opp[q]], 1.f);
+                        *at32(row, pull_x<LAT, q, V>(r, i)) =
+                            enc_store<ST, SR>(o[i][L::opp[q]], SR ? h[i] : 0u, L::opp[q]);
             }
         });
     }

@@ -104,6 +104,8 @@ struct StepArgs {
     Geometry g;
     Physics ph;
     int remap;          // XCD-contiguous block order
+    int sr;             // stochastic rounding of the stored 16-bit values
+    uint32_t sr_key;    // the step's key for the random bits of stochastic rounding
     const void *links;  // per-node link masks (nullable: no solids)
     const void *src;
     void *dst;
@@ -189,6 +191,8 @@ hipError_t launch_thermal(int mode, int storage, const ThermalArgs &a, int nbloc
 // Launchers (lbm_kernels.hip). Each returns hipSuccess or the launch error.
 // force: 0 no field, 1 E only, 2 E and B.
 hipError_t launch_step(int lattice, int storage, int force, const StepArgs &a, hipStream_t st);
+// the same with stochastic rounding (16-bit storage; a.sr set)
+hipError_t launch_step_sr(int lattice, int storage, int force, const StepArgs &a, hipStream_t st);
 // rho <-> mu of the weight (lbm_density.hip); to_mu selects the inverse
 hipError_t launch_density(int D, int stats, double theta, const double *in, double *out, size_t n, bool to_mu,
                           hipStream_t st);
@@ -225,6 +229,7 @@ hipError_t launch_adjoint(int lattice, int storage, bool mag, bool shift, const 
 // layout to the odd layout, phase 1 back. launch_canon writes the two-buffer layout of an
 // odd-layout state a.src into a.dst (a distinct buffer).
 hipError_t launch_step_aa(int lattice, int storage, int force, int phase, const StepArgs &a, hipStream_t st);
+hipError_t launch_step_aa_sr(int lattice, int storage, int force, int phase, const StepArgs &a, hipStream_t st);
 hipError_t launch_canon(int lattice, int storage, const StepArgs &a, hipStream_t st);
 hipError_t launch_seed(int lattice, const Geometry &g, float value_per_unit_e, int axis, float *lam,
                        hipStream_t st);

@@ -17,7 +17,7 @@
 // round-robin) works on one contiguous slab of the grid. Solid nodes are described by a
 // per-node link mask built once: bit a set when the pull of a into x bounces back, top
 // bit set when x itself is solid.
-#include "lbm_device.h"
+#include "lbm_step_kernels.h"
 
 #include <cstdlib>
 #include <mutex>
@@ -75,39 +75,6 @@ int row_block_threads(int nx, int V)
 }
 
 namespace {
-
-// ---------------------------------------------------------------------------------
-// K1: fused pull-stream + collide + force + partial bounce-back.
-// ---------------------------------------------------------------------------------
-template <int LAT, int ST, bool MASK, bool SOFT, int FORCE, int V, bool SLIP>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs a, int ntx, FastDiv div_ntx, int nblocks)
-{
-    using L = Lat<LAT>;
-    using T = typename Codec<ST>::T;
-    using LT = typename LinkMask<LAT>::T;
-    // without free-slip planes the reflection logic of every pull is compiled out where
-    // there are solids (measured on MI355X: FP16 duct +10 %, FP16 disks +8 %, with the
-    // loads issued before the link masks arrive); the kernels without solids keep the
-    // runtime test, whose code measured 3 % faster on the 4096^2 FP32 grid
-    if constexpr (MASK && !SLIP) a.g.slip = 0;
-    const int bid = block_order((int)blockIdx.x, nblocks, a.remap);
-    const Tile t = tile_of<V>(a.g, bid, ntx, div_ntx);
-    if (!t.valid) return;  // beyond the row (rows shorter than a block): no work
-    LT lk[V];
-    // Solid nodes go through the loads and the collision like fluid ones and only their
-    // stores are skipped (store_tile): leaving early would make every lane wait for its link
-    // mask before the population loads could issue, one more memory round trip per wave.
-    // Their pulls stay inside the state (the same row arithmetic as a fluid node's).
-    if (MASK) load_links<LAT, V>(static_cast<const LT *>(a.links), t.own, lk);
-    float d[V][L::Q];
-    gather_tile<LAT, ST, MASK, V>(a.g, static_cast<const T *>(a.src), 1.f, t, lk, d);  // stored units throughout
-    float sv[V];
-    if (SOFT) vload<LBM_F32, V>(at32(a.g.s, (unsigned)t.own), 1.f, sv);
-    float o[V][L::Q];
-#pragma unroll
-    for (int i = 0; i < V; ++i) collide<LAT, SOFT, FORCE>(a.ph, d[i], SOFT ? sv[i] : 0.f, o[i]);
-    store_tile<LAT, ST, MASK, V>(a.g, static_cast<typename Codec<ST>::T *>(a.dst), t, lk, o);
-}
 
 // ---------------------------------------------------------------------------------
 // Link masks: the top bit when x is solid (an obstacle of the mask or a node of a
@@ -786,49 +753,10 @@ __global__ __launch_bounds__(kBlock) void k_seed(Geometry g, float value, int ax
 // ---------------------------------------------------------------------------------
 // Launchers: runtime flags -> template instances.
 // ---------------------------------------------------------------------------------
-template <int LAT, int ST, int V>
-hipError_t step_v(int force, const StepArgs &a, hipStream_t st)
-{
-    const bool mask = a.links != nullptr, soft = a.g.s != nullptr;
-    const int ntx = (a.g.nx + kBlock * V - 1) / (kBlock * V);
-    const int nblocks = ntx * a.g.ny * a.g.nz;
-    const FastDiv div_ntx = make_fastdiv(ntx);
-    const dim3 grid(nblocks), block(row_block_threads(a.g.nx, V));
-    StepArgs b = a;
-    b.remap = remap_code(a.remap, ntx);
-#define LBM_STEP(M, S, F)                                                                                      \
-    do {                                                                                                       \
-        if (M && b.g.slip)                                                                                     \
-            hipLaunchKernelGGL((k_step<LAT, ST, M, S, F, V, M>), grid, block, 0, st, b, ntx, div_ntx, nblocks); \
-        else                                                                                                   \
-            hipLaunchKernelGGL((k_step<LAT, ST, M, S, F, V, false>), grid, block, 0, st, b, ntx, div_ntx,      \
-                               nblocks);                                                                       \
-    } while (0)
-#define LBM_STEP_F(M, S)   \
-    if (force == 0)        \
-        LBM_STEP(M, S, 0); \
-    else if (force == 1)   \
-        LBM_STEP(M, S, 1); \
-    else if (force == 2)   \
-        LBM_STEP(M, S, 2); \
-    else                   \
-        LBM_STEP(M, S, 3)
-    if (mask) {
-        if (soft) LBM_STEP_F(true, true); else LBM_STEP_F(true, false);
-    } else {
-        if (soft) LBM_STEP_F(false, true); else LBM_STEP_F(false, false);
-    }
-#undef LBM_STEP_F
-#undef LBM_STEP
-    return hipGetLastError();
-}
-
 template <int LAT, int ST>
-hipError_t step_lat_st(int force, const StepArgs &a, hipStream_t st)
+hipError_t step_nearest(int force, const StepArgs &a, hipStream_t st)
 {
-    const int v = step_vector_width(LAT, ST, a.g.nx);
-    if (v == 2) return step_v<LAT, ST, 2>(force, a, st);
-    return step_v<LAT, ST, 1>(force, a, st);
+    return step_lat_st<LAT, ST, false>(force, a, st);
 }
 
 template <int LAT, int ST>
@@ -907,7 +835,8 @@ hipError_t init_lat_st(const InitArgs &a, hipStream_t st)
 
 hipError_t launch_step(int lattice, int storage, int force, const StepArgs &a, hipStream_t st)
 {
-    LBM_DISPATCH(step_lat_st, force, a, st);
+    if (a.sr) return launch_step_sr(lattice, storage, force, a, st);
+    LBM_DISPATCH(step_nearest, force, a, st);
 }
 
 hipError_t launch_adjoint(int lattice, int storage, bool mag, bool shift, const AdjointArgs &a, hipStream_t st)

@@ -18,6 +18,7 @@ LATTICES = {"D2V9": 0, "D3V19": 1, "D3V15": 2, "D1V7": 3}
 STATS = {"fd": 0, "be": 1, "hermite": 2}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 FORCING = {"source": 0, "shift": 1}
+ROUNDING = {"nearest": 0, "stochastic": 1}
 SLIP_Y, SLIP_Z = 1, 2
 
 LBM_OK, LBM_EINVAL, LBM_EUNSUPPORTED, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
@@ -30,6 +31,7 @@ EXPORTS = [
     "lbm_export_f64", "lbm_set_fields", "lbm_set_tau", "lbm_adjoint_seed", "lbm_adjoint_step",
     "lbm_density_from_mu", "lbm_mu_from_density", "lbm_init_thermal", "lbm_thetabar", "lbm_energy",
     "lbm_speed_change", "lbm_destroy", "lbm_last_error", "lbm_status_string", "lbm_current_noalloc",
+    "lbm_set_step_index",
 ]
 
 
@@ -40,7 +42,7 @@ class LbmParams(ctypes.Structure):
         ("theta", ctypes.c_double), ("mu", ctypes.c_double), ("tau", ctypes.c_double),
         ("E", ctypes.c_double * 3), ("B", ctypes.c_double * 3), ("rho0", ctypes.c_double),
         ("dev_scale_log2", ctypes.c_int), ("forcing", ctypes.c_int), ("slip", ctypes.c_int),
-        ("order", ctypes.c_int),
+        ("order", ctypes.c_int), ("rounding", ctypes.c_int),
     ]
 
 
@@ -86,6 +88,7 @@ def load_library() -> ctypes.CDLL:
         lib.lbm_speed_change.argtypes = [vp, vp, vp, i, ctypes.POINTER(d)]
         lib.lbm_step.argtypes = [vp, i]
         lib.lbm_step_from.argtypes = [vp, vp, vp]
+        lib.lbm_set_step_index.argtypes = [vp, ctypes.c_ulonglong]
         lib.lbm_moments.argtypes = [vp, vp, vp]
         lib.lbm_current.argtypes = [vp, ctypes.POINTER(d)]
         lib.lbm_current_noalloc.argtypes = [vp, vp]
@@ -120,10 +123,10 @@ def _check(rc, handle=None):
 
 def make_params(lattice="D2V9", nx=1, ny=1, nz=1, tau=0.8, E=(0.0, 0.0, 0.0), B=(0.0, 0.0, 0.0),
                 storage="f32", dev_scale_log2=0, rho0=1.0, stats="fd", theta=1.0 / 270.0, mu=1.0,
-                forcing="source", slip=0, order=0) -> LbmParams:
+                forcing="source", slip=0, order=0, rounding="nearest") -> LbmParams:
     """forcing: "source" (xi-dependent source term) or "shift" (velocity shift);
     slip: free-slip wall planes, SLIP_Y | SLIP_Z; order: D1V7 equilibrium truncation,
-    3 or 4 (0 = 4)."""
+    3 or 4 (0 = 4); rounding of 16-bit stored values: "nearest" or "stochastic"."""
     p = LbmParams()
     p.lattice = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
     p.stats = STATS[stats] if isinstance(stats, str) else int(stats)
@@ -137,6 +140,7 @@ def make_params(lattice="D2V9", nx=1, ny=1, nz=1, tau=0.8, E=(0.0, 0.0, 0.0), B=
     p.forcing = FORCING[forcing] if isinstance(forcing, str) else int(forcing)
     p.slip = int(slip)
     p.order = int(order)
+    p.rounding = ROUNDING[rounding] if isinstance(rounding, str) else int(rounding)
     return p
 
 
@@ -209,14 +213,14 @@ class Simulation:
     def __init__(self, lattice="D2V9", nx=1, ny=1, nz=1, tau=0.8, E=(0.0, 0.0, 0.0), B=(0.0, 0.0, 0.0),
                  storage="f32", dev_scale_log2=0, rho0=1.0, stats="fd", theta=1.0 / 270.0, mu=1.0,
                  mask=None, s=None, device="cuda", forcing="source", slip=0, work=None, inplace=False,
-                 order=0):
+                 order=0, rounding="nearest"):
         import torch
 
         self.torch = torch
         self.lib = load_library()
         self.lattice = lattice
         self.params = make_params(lattice, nx, ny, nz, tau, E, B, storage, dev_scale_log2, rho0, stats, theta, mu,
-                                  forcing, slip, order)
+                                  forcing, slip, order, rounding)
         self.sizes = buffer_sizes(self.params)
         self.Q, self.D, self.e = lattice_info(lattice)
         self.N = nx * ny * nz
@@ -303,6 +307,11 @@ class Simulation:
 
     def step_from(self, src, dst):
         _check(self.lib.lbm_step_from(self.h, _ptr(src), _ptr(dst)), self.h)
+
+    def set_step_index(self, t):
+        """Index of the next step (lbm_set_step_index): selects the random bits of
+        stochastic rounding, so that recomputed steps repeat the forward run."""
+        _check(self.lib.lbm_set_step_index(self.h, int(t)), self.h)
 
     def moments(self):
         """(rho (N,), u (D, N)) float32 device tensors of the current state."""

@@ -14,12 +14,13 @@ from oracle.oracle import OracleModel
 from paper_1710_09472_amd import workloads as W
 
 
-def gpu_sim(wl: W.Workload, storage="f32", dev_scale_log2=0, E=None, B=None, inplace=False):
+def gpu_sim(wl: W.Workload, storage="f32", dev_scale_log2=0, E=None, B=None, inplace=False, rounding="nearest"):
     from paper_1710_09472_amd.lbm import Simulation
 
     sim = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, E=wl.E if E is None else E,
                      B=wl.B if B is None else B, storage=storage, dev_scale_log2=dev_scale_log2,
-                     mask=wl.mask, s=wl.s, forcing=wl.forcing, slip=wl.slip, inplace=inplace)
+                     mask=wl.mask, s=wl.s, forcing=wl.forcing, slip=wl.slip, inplace=inplace,
+                     rounding=rounding)
     sim.init(wl.rho, wl.u)
     return sim
 

@@ -136,6 +136,13 @@ def test_parameter_validation():
     assert _rc(lbm.make_params("D2V9", 8, 8, storage="f16", dev_scale_log2=41)) == lbm.LBM_EINVAL
     assert _rc(lbm.make_params("D2V9", 8, 8, rho0=0.0)) == lbm.LBM_EINVAL
     assert _rc(lbm.make_params(7, 8, 8)) == lbm.LBM_EINVAL
+    # stochastic rounding: 16-bit storage of D2V9/D3V19 only; unknown modes refused
+    for st in ("f16", "bf16"):
+        assert _rc(lbm.make_params("D2V9", 8, 8, storage=st, rounding="stochastic")) == 0
+        assert _rc(lbm.make_params("D3V19", 8, 8, 8, storage=st, rounding="stochastic")) == 0
+    assert _rc(lbm.make_params("D2V9", 8, 8, rounding="stochastic")) == lbm.LBM_EINVAL
+    assert _rc(lbm.make_params("D1V7", 64, storage="f16", theta=0.25, rounding="stochastic")) == lbm.LBM_EINVAL
+    assert _rc(lbm.make_params("D2V9", 8, 8, storage="f16", rounding=2)) == lbm.LBM_EINVAL
 
 
 def test_create_rejections_without_device_work():

@@ -38,7 +38,7 @@ def test_algorithmic_bytes():
 def _copy_sources(tmp: Path) -> Path:
     dst = tmp / "paper_1710_09472_amd" / "csrc"
     dst.mkdir(parents=True)
-    for name in ("lbm_device.h", "lbm_kernels.hip", "lbm_thermal.hip"):
+    for name in ("lbm_device.h", "lbm_step_kernels.h", "lbm_kernels.hip", "lbm_thermal.hip"):
         shutil.copy(ROOT / "paper_1710_09472_amd" / "csrc" / name, dst / name)
     return dst
 

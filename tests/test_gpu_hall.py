@@ -25,9 +25,10 @@ pytestmark = pytest.mark.gpu
 E, B, TAU, STEPS = (1e-6, 0.0, 0.0), (0.0, 0.0, 1e-3), 0.7, 5000
 
 
-def _gpu_profiles(nx, ny, nz, storage="f32", k=0):
+def _gpu_profiles(nx, ny, nz, storage="f32", k=0, rounding="nearest"):
     wl = W.hall_duct_3d(nx, ny, nz)
-    sim = lbm.Simulation("D3V19", nx, ny, nz, tau=TAU, E=E, B=B, mask=wl.mask, storage=storage, dev_scale_log2=k)
+    sim = lbm.Simulation("D3V19", nx, ny, nz, tau=TAU, E=E, B=B, mask=wl.mask, storage=storage, dev_scale_log2=k,
+                         rounding=rounding)
     sim.init(wl.rho)
     m0 = sim.current()[0]
     sim.step(STEPS)
@@ -90,8 +91,9 @@ def test_hall_profiles_full_duct(oracle_duct_profiles):
     assert abs(m1 / m0 - 1) < 1e-6
 
 
+@pytest.mark.parametrize("rounding", ["nearest", "stochastic"])
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
-def test_hall_profiles_full_duct_16bit(storage, oracle_duct_profiles):
+def test_hall_profiles_full_duct_16bit(storage, rounding, oracle_duct_profiles):
     """The full duct with 16-bit deviation storage after all 5000 steps against the oracle:
     the current profiles (max-norm over the cross-section, on the scale of max|<j_x>|) and
     the total current sum <j_x> (relative), stated and bounded. FP16 takes 2^k with max|d| 2^k
@@ -102,14 +104,17 @@ def test_hall_profiles_full_duct_16bit(storage, oracle_duct_profiles):
     steps (its viscous time is ~2e5 steps): every step adds ~5e-7 to the moving deviations
     (~1e-3), i.e. about half an FP16 ulp (2^-11 relative) and a sixteenth of a BF16 ulp,
     so round-to-nearest-even storage drops a growing share of the force increments as the
-    flow speeds up."""
+    flow speeds up. Stochastic rounding keeps them on average: measured FP16 profiles
+    4.8e-5 / 4.2e-5 / 3.5e-5, total current 5.2e-8; BF16 3.3e-4 / 3.1e-4 / 2.6e-4, total
+    current 3.9e-6."""
     po, dmax = oracle_duct_profiles
     k = int(np.floor(np.log2(4096.0 / dmax))) if storage == "f16" else 0
-    j, m0, m1, _ = _gpu_profiles(256, 128, 128, storage, k)
+    j, m0, m1, _ = _gpu_profiles(256, 128, 128, storage, k, rounding)
     p = j.mean(axis=3)
     err = np.abs(p - po).max(axis=(1, 2)) / np.abs(po[0]).max()
     ecur = abs(p[0].sum() / po[0].sum() - 1)
-    print(f"duct {storage}{f' x 2^{k}' if storage == 'f16' else ''}, {STEPS} steps: profile errors (x, y, z) {err}, "
-          f"total current {ecur:.2e}, mass {abs(m1 / m0 - 1):.1e}")
-    bound = {"f16": (1.5e-2, 8e-3), "bf16": (0.5, 0.4)}[storage]
+    print(f"duct {storage}{f' x 2^{k}' if storage == 'f16' else ''} {rounding}, {STEPS} steps: profile errors "
+          f"(x, y, z) {err}, total current {ecur:.2e}, mass {abs(m1 / m0 - 1):.1e}")
+    bound = {("f16", "nearest"): (1.5e-2, 8e-3), ("bf16", "nearest"): (0.5, 0.4),
+             ("f16", "stochastic"): (3e-4, 1e-5), ("bf16", "stochastic"): (2e-3, 1e-4)}[storage, rounding]
     assert (err < bound[0]).all() and ecur < bound[1], (err, ecur)
