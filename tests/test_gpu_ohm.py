@@ -56,9 +56,10 @@ def test_ohm_full_size_vs_oracle(kE):
     r = rows["rows"]
     mrow = wl.mask.reshape(wl.ny, wl.nx)[r] == 0
     res = {}
-    for st in ("f32", "f16", "bf16"):
+    for st, rounding in (("f32", "nearest"), ("f16", "nearest"), ("bf16", "nearest"), ("f16", "stochastic"),
+                         ("bf16", "stochastic")):
         k16 = f16_scale(kE) if st == "f16" else 0
-        sim = gpu_sim(wl, storage=st, dev_scale_log2=k16)
+        sim = gpu_sim(wl, storage=st, dev_scale_log2=k16, rounding=rounding)
         sim.step(wl.steps)
         tot = sim.current()
         rho, u = gpu_fields(sim)
@@ -70,14 +71,17 @@ def test_ohm_full_size_vs_oracle(kE):
         eu = max(eux, euy) / max(gold["max_abs"]["ux"], gold["max_abs"]["uy"])
         eM = abs(tot[0] / gold["M"] - 1)
         eP = abs(tot[1] / gold["Px"] - 1)
-        res[st] = (er, eu, eM, eP)
-        print(f"E = {kE}e-7 {st}{f' x 2^{k16}' if st == 'f16' else ''}: rho {er:.2e}, u {eu:.2e} (rows {list(r)}), "
-              f"M {eM:.2e}, P_x {eP:.2e}")
+        res[st if rounding == "nearest" else st + "-sr"] = (er, eu, eM, eP)
+        print(f"E = {kE}e-7 {st}{f' x 2^{k16}' if st == 'f16' else ''} {rounding}: rho {er:.2e}, u {eu:.2e} "
+              f"(rows {list(r)}), M {eM:.2e}, P_x {eP:.2e}")
     er, eu, eM, eP = res["f32"]
     assert er < 1e-5 and eu < 1e-5 and eM < 1e-5 and eP < 1e-5, res["f32"]
     assert res["f16"][3] < 1e-3, res["f16"]
     assert res["f16"][2] < 1e-5 and res["bf16"][2] < 1e-5
     assert res["bf16"][3] < 2e-2 and res["bf16"][1] < 5e-2, res["bf16"]
+    # stochastic rounding (measured at E = 1e-7: P_x 9.4e-7 FP16, 4.7e-6 BF16)
+    assert res["f16-sr"][3] < 1e-4 and res["f16-sr"][2] < 1e-5, res["f16-sr"]
+    assert res["bf16-sr"][3] < 1e-3 and res["bf16-sr"][1] < 5e-2, res["bf16-sr"]
 
 
 def test_ohm_sweep_full_size():
