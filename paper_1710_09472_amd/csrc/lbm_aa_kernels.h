@@ -178,8 +178,8 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_local(StepArgs a, int ntx, F
     const int bid = block_order((int)blockIdx.x, nblocks, a.remap);
     const Tile t = tile_of<V>(a.g, bid, ntx, div_ntx);
     if (!t.valid) return;
-    // solid nodes load and collide too (their own slots, in bounds) and store nothing:
-    // no lane waits for its link mask before its loads issue
+    // solid nodes load and collide too (their own slots, in bounds), so that no lane waits
+    // for its link mask before its loads issue; store_tile decides what they store
     LT lk[V];
     if (MASK) load_links<LAT, V>(static_cast<const LT *>(a.links), t.own, lk);
     T *f = static_cast<T *>(a.dst);

@@ -735,7 +735,8 @@ __device__ __forceinline__ void collide(const Physics &p, const float *D, float 
 // Store the post-collision deviations o of the fluid nodes of tile t at their own nodes
 // (slot q of x), and with the solid-slot convention each bounced one where the next pull
 // reads it: where x - e_q is solid, the value pulled into x as population q is
-// f*_qbar(x), kept in slot q of that solid node.
+// f*_qbar(x), kept in slot q of that solid node. With the own-slot convention solid nodes
+// beside fluid ones in the wave store their own slots too (read by no pull).
 // With SR the codes are rounded stochastically with the node hashes h (sr_node).
 template <int LAT, int ST, bool MASK, int V, bool SR = false>
 __device__ __forceinline__ void store_tile(const Geometry &g, typename Codec<ST>::T *__restrict__ dst, const Tile &t,
@@ -753,6 +754,18 @@ __device__ __forceinline__ void store_tile(const Geometry &g, typename Codec<ST>
         fluid[i] = !MASK || !(lk[i] & LinkMask<LAT>::solid);
         all_fluid = all_fluid && fluid[i];
         if (MASK && fluid[i]) links |= lk[i];
+    }
+    if constexpr (MASK && !kSolidSlotBB<ST>) {
+        // Own-slot convention: no pull reads a solid node's slots, so in a wave that holds a
+        // fluid node the solid lanes store their (unused) values too, and every store of the
+        // wave covers whole lines instead of leaving gaps at the obstacles; a wave of solid
+        // nodes only stores nothing. Measured on MI355X: FP32 2048^2 disks +5 %, in place
+        // +19 %; the paper's 3D Ohm sample +3 % / +5 %; the duct's wall rows unchanged.
+        bool any = false;
+#pragma unroll
+        for (int i = 0; i < V; ++i) any = any || fluid[i];
+        if (__builtin_amdgcn_ballot_w64(any) == 0) return;
+        all_fluid = true;
     }
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {

@@ -28,10 +28,10 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, int ntx, FastDiv di
     const Tile t = tile_of<V>(a.g, bid, ntx, div_ntx);
     if (!t.valid) return;  // beyond the row (rows shorter than a block): no work
     LT lk[V];
-    // Solid nodes go through the loads and the collision like fluid ones and only their
-    // stores are skipped (store_tile): leaving early would make every lane wait for its link
-    // mask before the population loads could issue, one more memory round trip per wave.
-    // Their pulls stay inside the state (the same row arithmetic as a fluid node's).
+    // Solid nodes go through the loads and the collision like fluid ones; store_tile
+    // decides which of their values are stored: leaving early would make every lane wait for
+    // its link mask before the population loads could issue, one more memory round trip per
+    // wave. Their pulls stay inside the state (the same row arithmetic as a fluid node's).
     if (MASK) load_links<LAT, V>(static_cast<const LT *>(a.links), t.own, lk);
     float d[V][L::Q];
     gather_tile<LAT, ST, MASK, V>(a.g, static_cast<const T *>(a.src), 1.f, t, lk, d);  // stored units throughout

@@ -11,7 +11,10 @@ It checks what the kernels rely on:
   locations that no fluid node reads or writes in that phase;
 * two in-place phases give exactly the populations of two two-buffer steps: every value
   any later pull reads is the same, with a collision stand-in that mixes all populations
-  of a node (index maps only; the node arithmetic is shared code).
+  of a node (index maps only; the node arithmetic is shared code);
+* with the own-slot convention (FP32) the obstacle nodes of a wave that holds fluid nodes
+  store their own slots too (whole-line stores), in the two-buffer step and in the local
+  phase: no pull reads those slots, so the results do not change.
 """
 import numpy as np
 import pytest
@@ -91,9 +94,31 @@ def collide(values, node, Q):
                      0.01 * (x + 3 * y + 7 * z + 11 * q) for q in k])
 
 
-def two_buffer_step(g: Grid, src: dict) -> dict:
+def stored_solids(g: Grid):
+    """Solid nodes that store their own slots: with the own-slot convention, those of a
+    wave (WAVE * V consecutive nodes of a row) that holds a fluid node; none otherwise."""
+    if g.solid_slot:
+        return set()
+    out = set()
+    for z in range(g.nz):
+        for y in range(g.ny):
+            for xw in range(0, g.nx, WAVE * g.V):
+                wave = [(x, y, z) for x in range(xw, min(g.nx, xw + WAVE * g.V))]
+                if any(g.fluid(*n) for n in wave):
+                    out.update(n for n in wave if not g.fluid(*n))
+    return out
+
+
+def two_buffer_step(g: Grid, src: dict, solid_stores=False) -> dict:
     dst = {}
+    junk_nodes = stored_solids(g) if solid_stores else set()
     for n in g.nodes():
+        if n in junk_nodes:  # whatever its loads give; stored in its own slots
+            f = np.array([src.get(g.pull_nobb(*n, q), 0.0) for q in range(g.Q)])
+            o = collide(f, n, g.Q) + 1e6
+            for q in range(g.Q):
+                dst[(q, n)] = o[q]
+            continue
         if not g.fluid(*n):
             continue
         f = np.array([src[g.P(*n, q)] for q in range(g.Q)])
@@ -133,9 +158,13 @@ def pull_phase_threads(g: Grid):
     return threads
 
 
-def local_phase_threads(g: Grid):
+def local_phase_threads(g: Grid, solid_stores=False):
     threads = []
+    junk_nodes = stored_solids(g) if solid_stores else set()
     for n in g.nodes():
+        if n in junk_nodes:  # loads its own slots, stores them
+            threads.append(([((g.opp[q], n), q, n) for q in range(g.Q)], [((q, n), q, n) for q in range(g.Q)]))
+            continue
         if not g.fluid(*n):
             continue
         reads, writes = [], []
@@ -221,9 +250,17 @@ def test_inplace_phases_race_free_and_equal_to_two_buffers(case, solid_slot, V):
     # every other location holds junk the fluid result must not depend on
     junk = {(q, n): 1e6 + rng.standard_normal() for n in g.nodes() for q in range(g.Q)}
     buf = {**junk, **s0}
-    p0, p1 = pull_phase_threads(g), local_phase_threads(g)
+    p0, p1 = pull_phase_threads(g), local_phase_threads(g, solid_stores=True)
     check_race_free(g, p0, "pull phase")
     check_race_free(g, p1, "local phase")
+    if not solid_slot:
+        # the two-buffer step with and without the obstacle nodes' stores
+        a = two_buffer_step(g, two_buffer_step(g, s0, True), True)
+        b = two_buffer_step(g, two_buffer_step(g, s0))
+        for n in g.nodes():
+            if g.fluid(*n):
+                for q in range(g.Q):
+                    assert a[g.P(*n, q)] == b[g.P(*n, q)], (n, q)
     # two in-place phases (two thread orders) against two two-buffer steps
     ref = two_buffer_step(g, two_buffer_step(g, s0))
     results = []
