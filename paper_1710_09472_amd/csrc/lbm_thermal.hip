@@ -47,23 +47,30 @@ struct ThermalNode {
 };
 
 // Deviations feq_a - rho0 what_a of the equilibrium of a node with moment deviations
-// drho = sum d, j = sum d e, dE = sum d e^2 (lattice units).
+// drho = sum d, j = sum d e, dE = sum d e^2 (lattice units). SC: the moments and feq are in
+// stored units (deviations x p.scale, a power of two); the node's fields rho, u, thetabar
+// are formed with p.inv_scale folded into 1/rho, and every other term keeps the stored
+// units. Scaling by a power of two is exact, so both give the same bits (the FP16 step
+// then decodes and encodes without a multiply per population).
+template <bool SC = false>
 __device__ __forceinline__ ThermalNode thermal_equilibrium(const ThermalPhysics &p, float drho, float j, float dE,
                                                            float *feq)
 {
 #pragma clang fp contract(off)  // every fused multiply-add is explicit: the same bits in every kernel
     ThermalNode m;
-    m.rho = p.rho0 + drho;
+    m.rho = SC ? __builtin_fmaf(drho, p.inv_scale, p.rho0) : p.rho0 + drho;  // one rounding either way
     const float inv = __builtin_amdgcn_rcpf(m.rho);  // v_rcp_f32 (1 ulp), as in the isothermal step
-    m.u = j * inv;
+    const float invs = SC ? inv * p.inv_scale : inv;
+    m.u = j * invs;
     const float u2 = m.u * m.u;
     // D = dE - T drho = rho (thetabar - T) + rho u^2   (sum rho0 what e^2 = rho0 T)
     const float D = dE - __builtin_fmaf(p.tb_hi, drho, p.tb_lo * drho);
-    const float dtb = __builtin_fmaf(D, inv, -u2);
+    const float dtb = __builtin_fmaf(D, invs, -u2);
     m.dtb = dtb;
     // second-order remainders of the targets dM_3, dM_4 (their linear parts are in pe, ko)
     const float r3 = j * __builtin_fmaf(3.0f, dtb, u2);
-    const float r4 = m.rho * __builtin_fmaf(u2, __builtin_fmaf(6.0f, dtb, u2) + p.k6, 3.0f * p.g0 * dtb * dtb);
+    const float rho_s = SC ? m.rho * p.scale : m.rho;
+    const float r4 = rho_s * __builtin_fmaf(u2, __builtin_fmaf(6.0f, dtb, u2) + p.k6, 3.0f * p.g0 * dtb * dtb);
     const float c0 = __builtin_fmaf(p.he[0], r4, __builtin_fmaf(p.pe[0], D, drho));
     const float c2 = __builtin_fmaf(p.he[1], r4, p.pe[1] * D);
     const float c4 = __builtin_fmaf(p.he[2], r4, p.pe[2] * D);
@@ -116,25 +123,31 @@ __device__ __forceinline__ float tload_nt(const TT<ST> *p, float inv_scale)
     return Codec<ST>::dec(__builtin_nontemporal_load(p), inv_scale);
 }
 
+// The step kernels work in stored units where the format has a scale (FP16: no multiply
+// in decoding and encoding); the other kernels decode to deviations.
+template <int ST>
+constexpr bool kStoredUnits = ST == LBM_F16;
+
 // The pre-collision populations of node x: slot q of x - e_q (the layout the two-buffer
 // step leaves, "even"), or, after the pull phase of the in-place step ("odd"), slot qbar
-// of x itself.
+// of x itself; decoded with inv_scale.
 template <int ST>
-__device__ __forceinline__ void thermal_pull(const ThermalArgs &a, int x, float *d)
+__device__ __forceinline__ void thermal_pull(const ThermalArgs &a, int x, float *d, float inv_scale)
 {
     const TT<ST> *src = static_cast<const TT<ST> *>(a.src);
 #pragma unroll
     for (int q = 0; q < kQ7; ++q)
-        d[q] = a.odd ? tload_nt<ST>(at32(src + (size_t)kOpp7[q] * a.stride, (unsigned)x), a.ph.inv_scale)
-                     : tload_nt<ST>(at32(src + (size_t)q * a.stride, wrap_shift(x, kE7[q], a.n)), a.ph.inv_scale);
+        d[q] = a.odd ? tload_nt<ST>(at32(src + (size_t)kOpp7[q] * a.stride, (unsigned)x), inv_scale)
+                     : tload_nt<ST>(at32(src + (size_t)q * a.stride, wrap_shift(x, kE7[q], a.n)), inv_scale);
 }
 
-// post-collision deviations of a node from its pre-collision ones
+// post-collision deviations of a node from its pre-collision ones (SC: stored units)
+template <bool SC>
 __device__ __forceinline__ void thermal_collide(const ThermalPhysics &p, const float *d, float *o)
 {
     float feq[kQ7], drho, j, dE;
     thermal_moments(d, drho, j, dE);
-    thermal_equilibrium(p, drho, j, dE, feq);
+    thermal_equilibrium<SC>(p, drho, j, dE, feq);
 #pragma unroll
     for (int q = 0; q < kQ7; ++q) o[q] = __builtin_fmaf(p.omega, feq[q] - d[q], d[q]);
 }
@@ -146,22 +159,23 @@ __global__ __launch_bounds__(kBlock) void k_thermal_step(ThermalArgs a)
     if (x >= a.n) return;
     const TT<ST> *src = static_cast<const TT<ST> *>(a.src);
     TT<ST> *dst = static_cast<TT<ST> *>(a.dst);
+    constexpr bool SC = kStoredUnits<ST>;
+    const float dsc = SC ? 1.f : a.ph.inv_scale, esc = SC ? 1.f : a.ph.scale;
     float d[kQ7], o[kQ7];
     if (x >= 3 && x + 3 < a.n) {
         // no wrap: the rest population is read once (non-temporal); the shifted ones stay
         // cached, since the lines at a tile's edges are shared with the neighbouring tiles
         // (measured 2 % faster than non-temporal loads throughout)
-        d[0] = tload_nt<ST>(at32(src, (unsigned)x), a.ph.inv_scale);
+        d[0] = tload_nt<ST>(at32(src, (unsigned)x), dsc);
 #pragma unroll
-        for (int q = 1; q < kQ7; ++q)
-            d[q] = Codec<ST>::dec(src[(size_t)q * a.stride + (unsigned)(x - kE7[q])], a.ph.inv_scale);
+        for (int q = 1; q < kQ7; ++q) d[q] = Codec<ST>::dec(src[(size_t)q * a.stride + (unsigned)(x - kE7[q])], dsc);
     } else {
-        thermal_pull<ST>(a, x, d);
+        thermal_pull<ST>(a, x, d, dsc);
     }
-    thermal_collide(a.ph, d, o);
+    thermal_collide<SC>(a.ph, d, o);
 #pragma unroll
     for (int q = 0; q < kQ7; ++q)
-        __builtin_nontemporal_store(Codec<ST>::enc(o[q], a.ph.scale), at32(dst + (size_t)q * a.stride, (unsigned)x));
+        __builtin_nontemporal_store(Codec<ST>::enc(o[q], esc), at32(dst + (size_t)q * a.stride, (unsigned)x));
 }
 
 // In-place step (one buffer, the AA pattern), phase 0: pull as the two-buffer step does
@@ -175,16 +189,18 @@ __global__ __launch_bounds__(kBlock) void k_thermal_aa_pull(ThermalArgs a)
     const int x = (int)(blockIdx.x * kBlock + threadIdx.x);
     if (x >= a.n) return;
     TT<ST> *f = static_cast<TT<ST> *>(a.dst);
+    constexpr bool SC = kStoredUnits<ST>;
+    const float dsc = SC ? 1.f : a.ph.inv_scale, esc = SC ? 1.f : a.ph.scale;
     float d[kQ7], o[kQ7];
     const bool interior = x >= 3 && x + 3 < a.n;
 #pragma unroll
     for (int q = 0; q < kQ7; ++q)
         d[q] = Codec<ST>::dec(f[(size_t)q * a.stride + (interior ? (unsigned)(x - kE7[q]) : wrap_shift(x, kE7[q], a.n))],
-                              a.ph.inv_scale);
-    thermal_collide(a.ph, d, o);
+                              dsc);
+    thermal_collide<SC>(a.ph, d, o);
 #pragma unroll
     for (int q = 0; q < kQ7; ++q)
-        __builtin_nontemporal_store(Codec<ST>::enc(o[q], a.ph.scale),
+        __builtin_nontemporal_store(Codec<ST>::enc(o[q], esc),
                                     at32(f + (size_t)kOpp7[q] * a.stride,
                                          interior ? (unsigned)(x + kE7[q]) : wrap_shift(x, -kE7[q], a.n)));
 }
@@ -197,13 +213,15 @@ __global__ __launch_bounds__(kBlock) void k_thermal_aa_local(ThermalArgs a)
     const int x = (int)(blockIdx.x * kBlock + threadIdx.x);
     if (x >= a.n) return;
     TT<ST> *f = static_cast<TT<ST> *>(a.dst);
+    constexpr bool SC = kStoredUnits<ST>;
+    const float dsc = SC ? 1.f : a.ph.inv_scale, esc = SC ? 1.f : a.ph.scale;
     float d[kQ7], o[kQ7];
 #pragma unroll
-    for (int q = 0; q < kQ7; ++q) d[q] = tload_nt<ST>(at32(f + (size_t)kOpp7[q] * a.stride, (unsigned)x), a.ph.inv_scale);
-    thermal_collide(a.ph, d, o);
+    for (int q = 0; q < kQ7; ++q) d[q] = tload_nt<ST>(at32(f + (size_t)kOpp7[q] * a.stride, (unsigned)x), dsc);
+    thermal_collide<SC>(a.ph, d, o);
 #pragma unroll
     for (int q = 0; q < kQ7; ++q)
-        __builtin_nontemporal_store(Codec<ST>::enc(o[q], a.ph.scale), at32(f + (size_t)q * a.stride, (unsigned)x));
+        __builtin_nontemporal_store(Codec<ST>::enc(o[q], esc), at32(f + (size_t)q * a.stride, (unsigned)x));
 }
 
 // Odd layout src -> even layout dst: g_q(y) = src slot qbar of y + e_q (stored values moved
@@ -248,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_thermal_fields(ThermalArgs a)
     const int x = (int)(blockIdx.x * kBlock + threadIdx.x);
     if (x >= a.n) return;
     float d[kQ7], feq[kQ7];
-    thermal_pull<ST>(a, x, d);
+    thermal_pull<ST>(a, x, d, a.ph.inv_scale);
     if (a.f64) {
 #pragma unroll
         for (int q = 0; q < kQ7; ++q) a.f64[(size_t)q * a.n + x] = a.ph.what_rho0[q] + (double)d[q];
@@ -271,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_thermal_partials(ThermalArgs a)
     double acc[3] = {0.0, 0.0, 0.0};
     for (int x = (int)(blockIdx.x * kBlock + threadIdx.x); x < a.n; x += (int)(gridDim.x * kBlock)) {
         float d[kQ7];
-        thermal_pull<ST>(a, x, d);
+        thermal_pull<ST>(a, x, d, a.ph.inv_scale);
         float drho, j, dE;
         thermal_moments(d, drho, j, dE);
         acc[0] += drho;
