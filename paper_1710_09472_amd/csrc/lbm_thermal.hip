@@ -178,6 +178,53 @@ __global__ __launch_bounds__(kBlock) void k_thermal_step(ThermalArgs a)
         __builtin_nontemporal_store(Codec<ST>::enc(o[q], esc), at32(dst + (size_t)q * a.stride, (unsigned)x));
 }
 
+// The same step with 16-bit storage, two nodes per thread (x0 = 2 i and x0 + 1; n even):
+// the two values a population pulls, from x0 - e and x0 + 1 - e, are adjacent, so one
+// 4-byte load fetches them (2-byte aligned for odd e: gfx9 global loads allow it), and the
+// stores are aligned 4-byte pairs. Threads whose pulls wrap around the ends load the
+// values one by one. The node arithmetic is that of k_thermal_step (the same bits).
+template <int ST>
+__global__ __launch_bounds__(kBlock) void k_thermal_step2(ThermalArgs a)
+{
+    static_assert(sizeof(TT<ST>) == 2, "pairs of 16-bit values");
+    using T = TT<ST>;
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    typedef uint32_t u32a2 __attribute__((aligned(2)));
+    const int x0 = 2 * (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (x0 >= a.n) return;
+    const T *src = static_cast<const T *>(a.src);
+    T *dst = static_cast<T *>(a.dst);
+    constexpr bool SC = kStoredUnits<ST>;
+    const float dsc = SC ? 1.f : a.ph.inv_scale, esc = SC ? 1.f : a.ph.scale;
+    float d0[kQ7], d1[kQ7], o0[kQ7], o1[kQ7];
+    if (x0 >= 3 && x0 + 4 < a.n) {
+#pragma unroll
+        for (int q = 0; q < kQ7; ++q) {
+            const T *p = at32(src + (size_t)q * a.stride, (unsigned)(x0 - kE7[q]));
+            // the rest population is read once (non-temporal); the shifted pairs share their
+            // lines with the neighbouring threads and tiles and stay cached
+            const uint32_t w = q == 0 ? __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(p))
+                                      : *reinterpret_cast<const u32a2 *>(p);
+            d0[q] = Codec<ST>::dec(__builtin_bit_cast(T, (uint16_t)w), dsc);
+            d1[q] = Codec<ST>::dec(__builtin_bit_cast(T, (uint16_t)(w >> 16)), dsc);
+        }
+    } else {
+        const int x1 = x0 + 1 < a.n ? x0 + 1 : x0;  // n even: x0 + 1 < n always
+#pragma unroll
+        for (int q = 0; q < kQ7; ++q) {
+            d0[q] = Codec<ST>::dec(*at32(src + (size_t)q * a.stride, wrap_shift(x0, kE7[q], a.n)), dsc);
+            d1[q] = Codec<ST>::dec(*at32(src + (size_t)q * a.stride, wrap_shift(x1, kE7[q], a.n)), dsc);
+        }
+    }
+    thermal_collide<SC>(a.ph, d0, o0);
+    thermal_collide<SC>(a.ph, d1, o1);
+#pragma unroll
+    for (int q = 0; q < kQ7; ++q) {
+        const T2 v = {Codec<ST>::enc(o0[q], esc), Codec<ST>::enc(o1[q], esc)};
+        __builtin_nontemporal_store(v, reinterpret_cast<T2 *>(at32(dst + (size_t)q * a.stride, (unsigned)x0)));
+    }
+}
+
 // In-place step (one buffer, the AA pattern), phase 0: pull as the two-buffer step does
 // (slot q of x - e_q), collide, and store g_q(x) where the opposite population was pulled
 // from, slot qbar of x + e_q; each node writes exactly the locations it read, which no
@@ -222,6 +269,81 @@ __global__ __launch_bounds__(kBlock) void k_thermal_aa_local(ThermalArgs a)
 #pragma unroll
     for (int q = 0; q < kQ7; ++q)
         __builtin_nontemporal_store(Codec<ST>::enc(o[q], esc), at32(f + (size_t)q * a.stride, (unsigned)x));
+}
+
+// The two in-place phases with 16-bit storage and two nodes per thread (n even), as
+// k_thermal_step2: the pull phase loads and stores shifted pairs (x0 -+ e, x0 + 1 -+ e) with
+// one 4-byte access each (2-byte aligned for odd e), the local phase aligned pairs;
+// threads whose pairs wrap around the ends go value by value. A thread writes exactly the
+// locations its two nodes read, as in the one-node kernels.
+template <int ST>
+__global__ __launch_bounds__(kBlock) void k_thermal_aa_pull2(ThermalArgs a)
+{
+    static_assert(sizeof(TT<ST>) == 2, "pairs of 16-bit values");
+    using T = TT<ST>;
+    typedef uint32_t u32a2 __attribute__((aligned(2)));
+    const int x0 = 2 * (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (x0 >= a.n) return;
+    T *f = static_cast<T *>(a.dst);
+    constexpr bool SC = kStoredUnits<ST>;
+    const float dsc = SC ? 1.f : a.ph.inv_scale, esc = SC ? 1.f : a.ph.scale;
+    float d0[kQ7], d1[kQ7], o0[kQ7], o1[kQ7];
+    const bool interior = x0 >= 3 && x0 + 4 < a.n;
+    if (interior) {
+#pragma unroll
+        for (int q = 0; q < kQ7; ++q) {
+            const uint32_t w = *reinterpret_cast<const u32a2 *>(at32(f + (size_t)q * a.stride, (unsigned)(x0 - kE7[q])));
+            d0[q] = Codec<ST>::dec(__builtin_bit_cast(T, (uint16_t)w), dsc);
+            d1[q] = Codec<ST>::dec(__builtin_bit_cast(T, (uint16_t)(w >> 16)), dsc);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < kQ7; ++q) {
+            d0[q] = Codec<ST>::dec(*at32(f + (size_t)q * a.stride, wrap_shift(x0, kE7[q], a.n)), dsc);
+            d1[q] = Codec<ST>::dec(*at32(f + (size_t)q * a.stride, wrap_shift(x0 + 1, kE7[q], a.n)), dsc);
+        }
+    }
+    thermal_collide<SC>(a.ph, d0, o0);
+    thermal_collide<SC>(a.ph, d1, o1);
+#pragma unroll
+    for (int q = 0; q < kQ7; ++q) {
+        const T c0 = Codec<ST>::enc(o0[q], esc), c1 = Codec<ST>::enc(o1[q], esc);
+        T *row = f + (size_t)kOpp7[q] * a.stride;
+        if (interior) {
+            const uint32_t w = (uint32_t)__builtin_bit_cast(uint16_t, c0) | ((uint32_t)__builtin_bit_cast(uint16_t, c1) << 16);
+            __builtin_nontemporal_store(w, reinterpret_cast<u32a2 *>(at32(row, (unsigned)(x0 + kE7[q]))));
+        } else {
+            __builtin_nontemporal_store(c0, at32(row, wrap_shift(x0, -kE7[q], a.n)));
+            __builtin_nontemporal_store(c1, at32(row, wrap_shift(x0 + 1, -kE7[q], a.n)));
+        }
+    }
+}
+
+template <int ST>
+__global__ __launch_bounds__(kBlock) void k_thermal_aa_local2(ThermalArgs a)
+{
+    static_assert(sizeof(TT<ST>) == 2, "pairs of 16-bit values");
+    using T = TT<ST>;
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    const int x0 = 2 * (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (x0 >= a.n) return;
+    T *f = static_cast<T *>(a.dst);
+    constexpr bool SC = kStoredUnits<ST>;
+    const float dsc = SC ? 1.f : a.ph.inv_scale, esc = SC ? 1.f : a.ph.scale;
+    float d0[kQ7], d1[kQ7], o0[kQ7], o1[kQ7];
+#pragma unroll
+    for (int q = 0; q < kQ7; ++q) {
+        const T2 v = __builtin_nontemporal_load(reinterpret_cast<const T2 *>(at32(f + (size_t)kOpp7[q] * a.stride, (unsigned)x0)));
+        d0[q] = Codec<ST>::dec(v[0], dsc);
+        d1[q] = Codec<ST>::dec(v[1], dsc);
+    }
+    thermal_collide<SC>(a.ph, d0, o0);
+    thermal_collide<SC>(a.ph, d1, o1);
+#pragma unroll
+    for (int q = 0; q < kQ7; ++q) {
+        const T2 v = {Codec<ST>::enc(o0[q], esc), Codec<ST>::enc(o1[q], esc)};
+        __builtin_nontemporal_store(v, reinterpret_cast<T2 *>(at32(f + (size_t)q * a.stride, (unsigned)x0)));
+    }
 }
 
 // Odd layout src -> even layout dst: g_q(y) = src slot qbar of y + e_q (stored values moved
@@ -316,6 +438,13 @@ hipError_t launch_thermal_st(int mode, const ThermalArgs &a, int nblocks_reduce,
     switch (mode) {
     case 0:
         if (!a.src || !a.dst || a.src == a.dst) return hipErrorInvalidValue;
+        if constexpr (ST != LBM_F32) {
+            if (a.n % 2 == 0) {  // two nodes per thread (measured on MI355X: see k_thermal_step2)
+                const int pairs = a.n / 2;
+                hipLaunchKernelGGL(k_thermal_step2<ST>, dim3((pairs + kBlock - 1) / kBlock), block, 0, st, a);
+                break;
+            }
+        }
         hipLaunchKernelGGL(k_thermal_step<ST>, grid, block, 0, st, a);
         break;
     case 1:
@@ -334,6 +463,16 @@ hipError_t launch_thermal_st(int mode, const ThermalArgs &a, int nblocks_reduce,
     case 5:
     case 6:
         if (!a.dst || a.src != a.dst) return hipErrorInvalidValue;
+        if constexpr (ST != LBM_F32) {
+            if (a.n % 2 == 0) {  // two nodes per thread
+                const dim3 g2((a.n / 2 + kBlock - 1) / kBlock);
+                if (mode == 5)
+                    hipLaunchKernelGGL(k_thermal_aa_pull2<ST>, g2, block, 0, st, a);
+                else
+                    hipLaunchKernelGGL(k_thermal_aa_local2<ST>, g2, block, 0, st, a);
+                break;
+            }
+        }
         if (mode == 5)
             hipLaunchKernelGGL(k_thermal_aa_pull<ST>, grid, block, 0, st, a);
         else
