@@ -277,7 +277,8 @@ int lbm_speed_change(lbm_t h, const float *u, float *speed, int have_previous, d
  * layout: post-collision populations of the previous step).
  * With one state buffer after an odd number of steps, lbm_get_state rearranges the
  * in-place layout into dst with a kernel (dst must not be state_a, LBM_EINVAL);
- * lbm_set_state restarts the in-place sequence from the two-buffer layout. Async. */
+ * lbm_set_state restarts the in-place sequence from the two-buffer layout and sets the
+ * step index to 0 (lbm_set_step_index). Async. */
 int lbm_get_state(lbm_t h, void *dst);
 int lbm_set_state(lbm_t h, const void *src);
 
