@@ -172,7 +172,8 @@ def inplace_extra(wl, storage: str, k: int, steps: int, warmup: int):
 
 def thermal_extra(steps: int, warmup: int):
     """Throughput of the fourth-order thermal step (D1V7, the 2^24-node thermal_1d
-    workload) and its HBM fraction from HIP events on the library's stream."""
+    workload; FP32 and FP16 storage, two buffers and in place) and its HBM fraction from
+    HIP events on the library's stream."""
     from paper_1710_09472_amd.lbm import Simulation
 
     wl = make_workload("thermal_1d")
@@ -186,11 +187,25 @@ def thermal_extra(steps: int, warmup: int):
     one.init(wl.rho, wl.u, wl.thetabar)
     w1, e1 = timed_steps(one, steps, warmup + (warmup % 2))
     one.close()
-    return {"workload": "thermal_1d: D1V7 2^24 nodes, K = 4, FP32", "MLUPS": round(wl.N * steps / w / 1e6, 1),
-            "ms_per_step": round(w / steps * 1e3, 5), "achieved_GBs": round(gbs, 1),
-            "hbm_frac": round(gbs / 8000.0, 4),
-            "inplace": {"MLUPS": round(wl.N * steps / w1 / 1e6, 1), "ms_per_step": round(w1 / steps * 1e3, 5),
-                        "achieved_GBs": round(alg / (e1 / steps) / 1e9, 1), "state_buffers": 1}}
+    out = {"workload": "thermal_1d: D1V7 2^24 nodes, K = 4, FP32", "MLUPS": round(wl.N * steps / w / 1e6, 1),
+           "ms_per_step": round(w / steps * 1e3, 5), "achieved_GBs": round(gbs, 1),
+           "hbm_frac": round(gbs / 8000.0, 4),
+           "inplace": {"MLUPS": round(wl.N * steps / w1 / 1e6, 1), "ms_per_step": round(w1 / steps * 1e3, 5),
+                       "achieved_GBs": round(alg / (e1 / steps) / 1e9, 1), "state_buffers": 1}}
+    # FP16 storage (x 2^17), two state buffers and in place
+    alg16 = algorithmic_bytes(wl, 7, 2)
+    for inplace in (False, True):
+        s16 = Simulation(wl.lattice, wl.nx, wl.ny, wl.nz, tau=wl.tau, theta=wl.theta, mu=wl.mu, storage="f16",
+                         dev_scale_log2=F16_SCALE["thermal_1d"], inplace=inplace)
+        s16.init(wl.rho, wl.u, wl.thetabar)
+        w16, e16 = timed_steps(s16, steps, warmup + (warmup % 2))
+        s16.close()
+        g16 = alg16 / (e16 / steps) / 1e9
+        out["f16_inplace" if inplace else "f16"] = {"MLUPS": round(wl.N * steps / w16 / 1e6, 1),
+                                                   "ms_per_step": round(w16 / steps * 1e3, 5),
+                                                   "achieved_GBs": round(g16, 1), "hbm_frac": round(g16 / 8000.0, 4),
+                                                   "dev_scale_log2": F16_SCALE["thermal_1d"]}
+    return out
 
 
 def adjoint_ratio(wl, steps: int, warmup: int, forcing: str = "source"):
