@@ -262,6 +262,24 @@ def adjoint_pipeline():
     out = {"workload": "soft_porous_3d: D3V19 128^3, mean s 0.2, E_x 1e-6, tau 0.75, 600 steps, K=50",
            "forward_ms_per_step": round(fwd * 1e3, 5), "reverse_ms_per_step": round(bwd * 1e3, 5),
            "ratio_to_forward": round(bwd / fwd, 3), "dJ_dEx": float(gE[0]), "dJ_dtau": float(gT)}
+    del cps
+    # every state kept (601 x 159 MB = 96 GB of the 288 GB): the reverse pass recomputes nothing
+    pk = Problem(wl.lattice, wl.nx, wl.ny, wl.nz, wl.steps, wl.rho, None, None, (0, 0, 0), keep_states=True)
+    for timed in (False, True):  # the first run fills torch's allocator cache
+        torch.cuda.synchronize()
+        k0 = time.perf_counter()
+        Jk, simk, states = forward_with_checkpoints(pk, wl.E, wl.tau, s)
+        torch.cuda.synchronize()
+        k1 = time.perf_counter()
+        gEk, gTk, gsk, _ = adjoint_gradients(pk, simk, states)
+        torch.cuda.synchronize()
+        k2 = time.perf_counter()
+        simk.close()
+        del states
+    fk, bk = (k1 - k0) / wl.steps, (k2 - k1) / wl.steps
+    out["kept_states"] = {"forward_ms_per_step": round(fk * 1e3, 5), "reverse_ms_per_step": round(bk * 1e3, 5),
+                          "ratio_to_forward": round(bk / fk, 3), "state_memory_GB": round((wl.steps + 1) * simk.sizes["state"] / 1e9, 1),
+                          "same_gradients": bool(torch.equal(gEk, gE) and torch.equal(gTk, gT) and torch.equal(gsk, gs))}
     # the stated error: against the FP64 oracle's central differences at the same size and
     # steps, stored in the repository (tests/golden/soft_porous_fd.json)
     gold_path = ROOT / "tests" / "golden" / "soft_porous_fd.json"

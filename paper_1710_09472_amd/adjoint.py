@@ -8,7 +8,10 @@ node after T time steps,
 and its backward pass runs the discrete adjoint (``lbm_adjoint_step``) with
 checkpoint-and-recompute: the forward pass keeps the state every K steps; the backward
 pass restores each checkpoint, recomputes the K states of that segment with
-``lbm_step_from`` and walks them in reverse. Gradients: dJ/dE (3), dJ/dtau and the
+``lbm_step_from`` and walks them in reverse. With ``keep_states`` the forward pass writes
+every state into its own buffer (``lbm_step_from`` from one to the next, no copies) and
+the backward pass recomputes nothing: T + 1 states of memory (the 128^3 D3V19 workload's
+600 steps: 96 GB, within one MI355X's 288 GB) for a reverse pass of adjoint steps only. Gradients: dJ/dE (3), dJ/dtau and the
 field dJ/ds of the partial bounce-back fraction. All arithmetic runs in the library's
 kernels; this module only orders the calls and owns the buffers (torch tensors). Both
 forcing schemes (``Problem.forcing``) and the free-slip wall planes (``Problem.slip``)
@@ -36,6 +39,7 @@ class Problem:
     mask: np.ndarray | None = None  # (N,) uint8
     B: tuple = (0.0, 0.0, 0.0)
     checkpoint: int = 50
+    keep_states: bool = False       # keep all T + 1 states: no recompute in the reverse pass
     axis: int = 0
     forcing: str = "source"         # "source" (Sec. 7) or "shift" (eq. (u-update-force-term-eq))
     slip: int = 0                   # free-slip wall planes (Sec. 9.4): bit 0 y, bit 1 z
@@ -53,9 +57,20 @@ def _make_sim(pb: Problem, E, tau, s):
 
 def forward_with_checkpoints(pb: Problem, E, tau, s):
     """Run T steps; return (J, sim, checkpoints) where checkpoints[i] is the state at
-    step i*K (the state whose pull gives f(i*K))."""
+    step i*K (the state whose pull gives f(i*K)), or, with keep_states, at step i for
+    every i = 0..T."""
     sim = _make_sim(pb, E, tau, s)
     sim.init(pb.rho, pb.u)
+    if pb.keep_states:
+        states = [sim.get_state()]
+        sim.set_step_index(0)
+        for _ in range(pb.steps):
+            nxt = sim.new_state(zero=False)  # written by the step where any pull reads
+            sim.step_from(states[-1], nxt)
+            states.append(nxt)
+        sim.set_state(states[-1])  # the totals of f(T)
+        tot = sim.current()
+        return tot[1 + pb.axis] / pb.N, sim, states
     cps = []
     for t0 in range(0, pb.steps, pb.checkpoint):
         cps.append(sim.get_state())
@@ -72,8 +87,13 @@ def adjoint_gradients(pb: Problem, sim: Simulation, cps):
     lam = [sim.adjoint_seed(pb.axis, pb.N), sim.new_adjoint()]
     gsc = torch.zeros(4, dtype=torch.float64, device=dev)
     gs = torch.zeros(pb.N, dtype=torch.float32, device=dev) if sim.s is not None else None
-    seg_bufs = [sim.new_state() for _ in range(K)]
     cur = 0
+    if pb.keep_states:  # every state kept by the forward pass: adjoint steps only
+        for t in range(pb.steps - 1, -1, -1):
+            sim.adjoint_step(cps[t], lam[cur], lam[cur ^ 1], gs, gsc if t == 0 else None)
+            cur ^= 1
+        return gsc[:3].clone(), gsc[3].clone(), gs, lam[cur]
+    seg_bufs = [sim.new_state() for _ in range(K)]
     nseg = len(cps)
     for i in range(nseg - 1, -1, -1):
         t0 = i * K

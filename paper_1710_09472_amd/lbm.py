@@ -376,7 +376,11 @@ class Simulation:
         _check(self.lib.lbm_export_f64(self.h, _ptr(state), _ptr(out)), self.h)
         return out.reshape(self.Q, self.N)
 
-    def new_state(self):
+    def new_state(self, zero=True):
+        """A state buffer of state_bytes (zero-filled, or left as allocated with zero=False:
+        a step writes every location a later pull reads)."""
+        if not zero:
+            return self.torch.empty(self.sizes["state"], dtype=self.torch.uint8, device=self.device)
         return self.torch.zeros(self.sizes["state"], dtype=self.torch.uint8, device=self.device)
 
     def get_state(self, dst=None):

@@ -211,6 +211,25 @@ def test_inplace_handle_gives_the_same_gradients():
         assert torch.equal(a, b), (a, b)
 
 
+def test_kept_states_give_the_same_gradients():
+    """keep_states (every forward state in its own buffer, no recompute in the reverse
+    pass) gives the checkpointed pass's J and gradients bit for bit: the forward states are
+    the same steps, and the adjoint steps run in the same order on them."""
+    wl = _wl(CASES[5], seed=35)  # 3D, obstacles, soft s, B, y+z slip planes
+    out = []
+    for keep in (False, True):
+        pb = Problem(wl.lattice, wl.nx, wl.ny, wl.nz, 13, wl.rho, wl.u, wl.mask, wl.B, checkpoint=5,
+                     slip=CASES[5][8], keep_states=keep)
+        E = torch.tensor(wl.E, dtype=torch.float64, device="cuda", requires_grad=True)
+        tau = torch.tensor(wl.tau, dtype=torch.float64, device="cuda", requires_grad=True)
+        s = torch.tensor(wl.s, dtype=torch.float32, device="cuda", requires_grad=True)
+        J = mean_current(E, tau, s, pb)
+        J.backward()
+        out.append((J.detach().cpu(), E.grad.cpu(), tau.grad.cpu(), s.grad.cpu()))
+    for a, b in zip(*out):
+        assert torch.equal(a, b), (a, b)
+
+
 @pytest.mark.parametrize("forcing", ["source", "shift"])
 def test_adjoint_step_full_size_sampled_rows(forcing):
     """The adjoint step at 4096^2 in the configuration the benchmark times (tau 0.6,
