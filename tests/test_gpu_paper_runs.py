@@ -48,6 +48,41 @@ def test_paper_poiseuille_viscosity(tau, lattice):
     assert resid < 1e-3
 
 
+def _nu_fit(wl, u):
+    ux = u[0].reshape(wl.ny, wl.nx)[1:-1]
+    prof = ux.mean(axis=1)
+    H = wl.ny - 2.0
+    yp = np.arange(1, wl.ny - 1) - 0.5
+    shape = yp * (H - yp)
+    alpha = float(prof @ shape / (shape @ shape))
+    return wl.E[0] / (2 * alpha), np.linalg.norm(prof - alpha * shape) / np.linalg.norm(prof)
+
+
+@pytest.mark.parametrize("tau", [0.8, 2.0])
+def test_paper_poiseuille_16bit_storage(tau):
+    """The same 2D channel (10^6 steps) with 16-bit deviation storage. Each step adds
+    E = 1e-8 to deviations of ~1e-4 near the end, far below half a unit of FP16 (x 2^25)
+    or BF16, so round to nearest loses the increments once the flow has grown and the fit
+    is off; stochastic rounding keeps them on average and the fit recovers (tau - 1/2)/3 as
+    in FP32 (both printed; stochastic rounding bounded). Measured on MI355X, fitted nu over
+    (tau - 1/2)/3 at tau = 0.8 / 2.0: round to nearest FP16 9.8 / 4.3, BF16 160 / 32 (the
+    flow stalls); stochastic rounding FP16 1.0019 / 0.9997, BF16 1.0020 / 1.0000, parabola
+    residuals 9e-5 (FP16) and 4e-4 (BF16)."""
+    wl = W.poiseuille_paper_2d(tau=tau)
+    nu = (tau - 0.5) / 3.0
+    for storage, k in (("f16", 25), ("bf16", 0)):
+        for rounding in ("nearest", "stochastic"):
+            sim = gpu_sim(wl, storage=storage, dev_scale_log2=k, rounding=rounding)
+            sim.step(wl.steps)
+            _, u = gpu_fields(sim)
+            sim.close()
+            nu_fit, resid = _nu_fit(wl, u)
+            print(f"{storage} {rounding} tau {tau}: nu fit / ((tau - 1/2)/3) = {nu_fit / nu:.5f}, "
+                  f"parabola residual {resid:.2e}")
+            if rounding == "stochastic":
+                assert abs(nu_fit / nu - 1) < 1e-2 and resid < 2e-3, (storage, nu_fit / nu, resid)
+
+
 def test_paper_ohm_linearity():
     ratios = []
     for k in range(1, 9):
