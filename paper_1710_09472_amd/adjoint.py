@@ -15,7 +15,10 @@ the backward pass recomputes nothing: T + 1 states of memory (the 128^3 D3V19 wo
 field dJ/ds of the partial bounce-back fraction. All arithmetic runs in the library's
 kernels; this module only orders the calls and owns the buffers (torch tensors). Both
 forcing schemes (``Problem.forcing``) and the free-slip wall planes (``Problem.slip``)
-are covered; J and the seed exclude the wall planes, which are solid.
+are covered; J and the seed exclude the wall planes, which are solid. With 16-bit forward
+states (``Problem.storage``) the gradients are those of the stored model with its encoding
+taken as the identity; with stochastic rounding the recomputed segments repeat the forward
+run's bits through the step index (``lbm_set_step_index``).
 """
 from __future__ import annotations
 
@@ -44,6 +47,9 @@ class Problem:
     forcing: str = "source"         # "source" (Sec. 7) or "shift" (eq. (u-update-force-term-eq))
     slip: int = 0                   # free-slip wall planes (Sec. 9.4): bit 0 y, bit 1 z
     inplace: bool = False           # one state buffer (checkpoints still in two-buffer layout)
+    storage: str = "f32"            # forward states in "f32", "f16" (x 2^dev_scale_log2) or "bf16"
+    dev_scale_log2: int = 0
+    rounding: str = "nearest"       # of 16-bit stored values: "nearest" or "stochastic"
 
     @property
     def N(self):
@@ -52,7 +58,8 @@ class Problem:
 
 def _make_sim(pb: Problem, E, tau, s):
     return Simulation(pb.lattice, pb.nx, pb.ny, pb.nz, tau=float(tau), E=[float(v) for v in E], B=pb.B,
-                      mask=pb.mask, s=s, forcing=pb.forcing, slip=pb.slip, inplace=pb.inplace)
+                      mask=pb.mask, s=s, forcing=pb.forcing, slip=pb.slip, inplace=pb.inplace,
+                      storage=pb.storage, dev_scale_log2=pb.dev_scale_log2, rounding=pb.rounding)
 
 
 def forward_with_checkpoints(pb: Problem, E, tau, s):

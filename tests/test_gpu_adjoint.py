@@ -230,6 +230,36 @@ def test_kept_states_give_the_same_gradients():
         assert torch.equal(a, b), (a, b)
 
 
+@pytest.mark.parametrize("storage,k,rounding", [("f16", 14, "stochastic"), ("bf16", 0, "stochastic"),
+                                                ("f16", 14, "nearest")])
+def test_16bit_forward_states_recompute_the_same_bits(storage, k, rounding):
+    """16-bit forward states: the checkpointed pass (K = 5, segments recomputed from the
+    step index of their checkpoint) and the kept-state pass give the same J and gradients
+    bit for bit, also with stochastic rounding (a wrong step index in the recompute would
+    round differently); and the gradients stay close to the FP32 ones (the 16-bit forward
+    model differs from the FP32 one by its rounding). Measured against FP32 forward states
+    (max-norm relative): FP16 J 9e-6, dJ/dE 3e-7, dJ/dtau 1.3e-3, dJ/ds 7e-5; BF16 J 3e-5,
+    dJ/dE 3e-6, dJ/dtau 2.9e-3, dJ/ds 5e-4."""
+    wl = _wl(CASES[5], seed=36)  # 3D, obstacles, soft s, B, y+z slip planes
+    out = []
+    for keep, st, kk, rnd in ((False, storage, k, rounding), (True, storage, k, rounding), (False, "f32", 0, "nearest")):
+        pb = Problem(wl.lattice, wl.nx, wl.ny, wl.nz, 13, wl.rho, wl.u, wl.mask, wl.B, checkpoint=5,
+                     slip=CASES[5][8], keep_states=keep, storage=st, dev_scale_log2=kk, rounding=rnd)
+        E = torch.tensor(wl.E, dtype=torch.float64, device="cuda", requires_grad=True)
+        tau = torch.tensor(wl.tau, dtype=torch.float64, device="cuda", requires_grad=True)
+        s = torch.tensor(wl.s, dtype=torch.float32, device="cuda", requires_grad=True)
+        J = mean_current(E, tau, s, pb)
+        J.backward()
+        out.append((J.detach().cpu(), E.grad.cpu(), tau.grad.cpu(), s.grad.cpu()))
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b), (a, b)
+    names = ("J", "dJ/dE", "dJ/dtau", "dJ/ds")
+    for name, a, b in zip(names, out[0], out[2]):
+        rel = float((a.double() - b.double()).abs().max() / b.double().abs().max())
+        print(f"{storage} {rounding}: {name} against FP32 forward states {rel:.2e}")
+        assert rel < (1.5e-2 if storage == "bf16" else 5e-3), (name, rel)
+
+
 @pytest.mark.parametrize("forcing", ["source", "shift"])
 def test_adjoint_step_full_size_sampled_rows(forcing):
     """The adjoint step at 4096^2 in the configuration the benchmark times (tau 0.6,
