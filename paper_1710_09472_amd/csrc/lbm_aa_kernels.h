@@ -168,6 +168,81 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_pull(StepArgs a, int ntx, Fa
     });
 }
 
+// Phase 0 without solids, 16-bit storage, two nodes per thread taken one node to the right
+// (xa = x0 + 1, xb = x0 + 2 mod nx): the pairs a population pulls from and stores to start
+// at x0 (towards +x pulls, towards -x stores), x0 + 2 mod nx (the other way) or x0 + 1
+// (unshifted), so the x-shifted accesses, six of nine, are aligned 4-byte pairs and only
+// the unshifted ones straddle; the last thread of a row (xb = 0) goes value by value for
+// those. Same node arithmetic and same locations per node as k_step_aa_pull.
+template <int LAT, int ST, bool SOFT, int FORCE, bool SR>
+__global__ __launch_bounds__(kBlock) void k_step_aa_pull_odd(StepArgs a, int ntx, FastDiv div_ntx, int nblocks)
+{
+    static_assert(LAT == LBM_D2V9 && ST != LBM_F32, "16-bit D2V9 pairs");
+    using L = Lat<LAT>;
+    using T = typename Codec<ST>::T;
+    typedef uint32_t u32a2 __attribute__((aligned(2)));
+    const int bid = block_order((int)blockIdx.x, nblocks, a.remap);
+    const Tile t = tile_of<2>(a.g, bid, ntx, div_ntx);
+    if (!t.valid) return;
+    const unsigned nx = (unsigned)a.g.nx;
+    const unsigned x0 = (unsigned)t.x0, xa = x0 + 1u, xb = x0 + 2u == nx ? 0u : x0 + 2u;
+    const bool last = xb == 0u;
+    const unsigned rowbase = (unsigned)(t.own - t.x0);  // node index of x = 0 in this row
+    T *f = static_cast<T *>(a.dst);
+    const PullRows r = pull_rows<2>(a.g, t);
+    auto pair_at = [&](int q) -> unsigned {  // first element of the pair node xa pulls q from
+        return L::ex[q] > 0 ? x0 : (L::ex[q] < 0 ? xb : xa);
+    };
+    float d[2][L::Q];
+    for_q<L::Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const T *row = f + pull_row<LAT, q>(a.g, t, r);
+        uint32_t w;
+        if constexpr (L::ex[q] == 0) {
+            if (!last) {
+                w = *reinterpret_cast<const u32a2 *>(at32(row, xa));
+            } else {
+                w = (uint32_t)__builtin_bit_cast(uint16_t, *at32(row, xa)) |
+                    ((uint32_t)__builtin_bit_cast(uint16_t, *at32(row, 0u)) << 16);
+            }
+        } else {
+            w = *reinterpret_cast<const uint32_t *>(at32(row, pair_at(q)));
+        }
+        d[0][q] = Codec<ST>::dec(__builtin_bit_cast(T, (uint16_t)w), 1.f);
+        d[1][q] = Codec<ST>::dec(__builtin_bit_cast(T, (uint16_t)(w >> 16)), 1.f);
+    });
+    float sv[2] = {0.f, 0.f};
+    if (SOFT) {
+        sv[0] = *at32(a.g.s, rowbase + xa);
+        sv[1] = *at32(a.g.s, rowbase + xb);
+    }
+    float o[2][L::Q];
+    collide<LAT, SOFT, FORCE>(a.ph, d[0], sv[0], o[0]);
+    collide<LAT, SOFT, FORCE>(a.ph, d[1], sv[1], o[1]);
+    uint32_t h[2] = {0u, 0u};
+    if (SR) {
+        h[0] = sr_node(rowbase + xa, a.sr_key);
+        h[1] = sr_node(rowbase + xb, a.sr_key);
+    }
+    for_q<L::Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int qb = L::opp[q];
+        T *row = f + pull_row<LAT, qb>(a.g, t, r);  // P(x, qbar): slot qbar of x + e_q
+        const uint32_t P = pack_pair<ST, SR>(o[0][q], o[1][q], h[0], h[1], q);
+        if constexpr (L::ex[q] == 0) {
+            if (!last) {
+                __builtin_nontemporal_store(P, reinterpret_cast<u32a2 *>(at32(row, xa)));
+            } else {
+                __builtin_nontemporal_store((uint16_t)P, reinterpret_cast<uint16_t *>(at32(row, xa)));
+                __builtin_nontemporal_store((uint16_t)(P >> 16), reinterpret_cast<uint16_t *>(at32(row, 0u)));
+            }
+        } else {
+            // the pair node xa pulls qbar from is where g_q(xa), g_q(xb) go
+            __builtin_nontemporal_store(P, reinterpret_cast<uint32_t *>(at32(row, pair_at(qb))));
+        }
+    });
+}
+
 // Phase 1: read the streamed populations of the node, collide, store in place.
 template <int LAT, int ST, bool MASK, bool SOFT, int FORCE, int V, bool SLIP, bool SR>
 __global__ __launch_bounds__(kBlock) void k_step_aa_local(StepArgs a, int ntx, FastDiv div_ntx, int nblocks)
@@ -209,6 +284,13 @@ hipError_t aa_v(int force, int phase, const StepArgs &a, hipStream_t st)
     StepArgs b = a;
     b.remap = remap_code(a.remap, ntx);
 #define LBM_AA_SL(M, S, F, SL)                                                                                   \
+    if constexpr (!M && LAT == LBM_D2V9 && ST != LBM_F32 && V == 2) {                                           \
+        if (phase == 0) {                                                                                       \
+            hipLaunchKernelGGL((k_step_aa_pull_odd<LAT, ST, S, F, SR>), grid, block, 0, st, b, ntx, div_ntx,     \
+                               nblocks);                                                                        \
+            break;                                                                                              \
+        }                                                                                                       \
+    }                                                                                                           \
     if (phase == 0)                                                                                             \
         hipLaunchKernelGGL((k_step_aa_pull<LAT, ST, M, S, F, V, SL, SR>), grid, block, 0, st, b, ntx, div_ntx,  \
                            nblocks);                                                                            \
