@@ -6,9 +6,10 @@ It checks what the kernels rely on:
 * race freedom: within a phase, every location is written by at most one thread, and no
   thread reads a location that another thread of the phase writes (so the phase gives the
   same result in any order of its threads);
-* with 16-bit storage and two nodes per thread, the obstacle nodes that take part in the
-  pull phase (a wave leaves only when all its nodes are solid) read and write only
-  locations that no fluid node reads or writes in that phase;
+* with 16-bit storage and two nodes per thread (pairs starting at even x, or one node to
+  the right as the pull phase without solids takes them), the obstacle nodes that take
+  part in the pull phase (a wave leaves only when all its nodes are solid) read and write
+  only locations that no fluid node reads or writes in that phase;
 * two in-place phases give exactly the populations of two two-buffer steps: every value
   any later pull reads is the same, with a collision stand-in that mixes all populations
   of a node (index maps only; the node arithmetic is shared code);
@@ -132,11 +133,13 @@ def two_buffer_step(g: Grid, src: dict, solid_stores=False) -> dict:
     return dst
 
 
-def pull_phase_threads(g: Grid):
+def pull_phase_threads(g: Grid, odd=False):
     """(reads, writes) of every thread of the pull phase; writes as (location, q, node).
     Rows of free-slip wall planes leave at once; in every other row the threads load and
     collide, fluid nodes store, and with two nodes per thread (16-bit) pairs are stored
-    whole, obstacle nodes included (in waves of obstacles only, too)."""
+    whole, obstacle nodes included (in waves of obstacles only, too). odd: the thread's
+    pair is taken one node to the right, (x0 + 1, x0 + 2 mod nx), as the 16-bit pull phase
+    without solids does."""
     threads = []
     for z in range(g.nz):
         for y in range(g.ny):
@@ -144,7 +147,7 @@ def pull_phase_threads(g: Grid):
                 continue
             for xw in range(0, g.nx, WAVE * g.V):  # one wave
                 for x0 in range(xw, min(g.nx, xw + WAVE * g.V), g.V):
-                    tn = [(x0 + i, y, z) for i in range(g.V)]
+                    tn = [((x0 + i + (1 if odd else 0)) % g.nx, y, z) for i in range(g.V)]
                     pairs = g.V == 2 and g.solid_slot
                     reads, writes = [], []
                     for n in tn:
@@ -230,9 +233,10 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("solid_slot,V", [(False, 1), (True, 1), (True, 2)], ids=["own-slot", "solid-slot", "pairs"])
+@pytest.mark.parametrize("solid_slot,V,odd", [(False, 1, False), (True, 1, False), (True, 2, False), (True, 2, True)],
+                         ids=["own-slot", "solid-slot", "pairs", "pairs-odd"])
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-{c[1][0]}x{c[1][1]}x{c[1][2]}-slip{c[3]}" for c in CASES])
-def test_inplace_phases_race_free_and_equal_to_two_buffers(case, solid_slot, V):
+def test_inplace_phases_race_free_and_equal_to_two_buffers(case, solid_slot, V, odd):
     lattice, (nx, ny, nz), phi, slip, seed = case[:5]
     if V == 2 and (lattice != "D2V9" or nx % 2):
         pytest.skip("two nodes per thread: 16-bit D2V9 rows of even length")
@@ -250,7 +254,7 @@ def test_inplace_phases_race_free_and_equal_to_two_buffers(case, solid_slot, V):
     # every other location holds junk the fluid result must not depend on
     junk = {(q, n): 1e6 + rng.standard_normal() for n in g.nodes() for q in range(g.Q)}
     buf = {**junk, **s0}
-    p0, p1 = pull_phase_threads(g), local_phase_threads(g, solid_stores=True)
+    p0, p1 = pull_phase_threads(g, odd=odd), local_phase_threads(g, solid_stores=True)
     check_race_free(g, p0, "pull phase")
     check_race_free(g, p1, "local phase")
     if not solid_slot:
