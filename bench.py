@@ -485,8 +485,8 @@ def cpu_baseline(wl, target_s: float = 12.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="throughput_2d", choices=sorted(WORKLOAD_DESC))
     ap.add_argument("--storage", default="f32", choices=("f32", "f16", "bf16"))
     ap.add_argument("--rounding", default="nearest", choices=("nearest", "stochastic"),
