@@ -74,8 +74,8 @@ __device__ __forceinline__ void store_pair_shifted(uint16_t *row, const PullRows
 }
 
 // Phase 0: pull, collide, store back where the opposite population was pulled from.
-// V nodes per thread as in the two-buffer step, except that the in-place step with solids
-// takes one (step_vector_width); the node arithmetic is the same either way. The
+// V nodes per thread as in the two-buffer step (the local phase with solids takes one,
+// step_vector_width); the node arithmetic is the same either way. The
 // stores of x-shifted populations are shifted like their loads: one value at a time,
 // or, with 16-bit storage and two nodes per thread, one 4-byte store per pair.
 template <int LAT, int ST, bool MASK, bool SOFT, int FORCE, int V, bool SLIP, bool SR>
@@ -328,7 +328,8 @@ hipError_t aa_v(int force, int phase, const StepArgs &a, hipStream_t st)
 template <int LAT, int ST, bool SR>
 hipError_t aa_lat_st(int force, int phase, const StepArgs &a, hipStream_t st)
 {
-    if (step_vector_width(LAT, ST, a.g.nx, a.links != nullptr) == 2) return aa_v<LAT, ST, 2, SR>(force, phase, a, st);
+    if (step_vector_width(LAT, ST, a.g.nx, a.links != nullptr && phase == 1) == 2)
+        return aa_v<LAT, ST, 2, SR>(force, phase, a, st);
     return aa_v<LAT, ST, 1, SR>(force, phase, a, st);
 }
 

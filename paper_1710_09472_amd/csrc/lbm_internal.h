@@ -220,7 +220,7 @@ hipError_t launch_speed_change(const float *u, int D, int N, float *speed, int h
                                int nblocks, hipStream_t st);
 hipError_t launch_reduce_final(const double *partials, int nparts, int ncomp, double *out,
                                int accumulate, hipStream_t st, double *stage);
-int step_vector_width(int lattice, int storage, int nx, bool inplace_solids = false);
+int step_vector_width(int lattice, int storage, int nx, bool local_phase_solids = false);
 int use_xcd_remap(int lattice, bool mask, bool soft);
 int remap_code(int remap, int ntx);
 // shift: the adjoint of the velocity-shift forcing (k_adjoint_shift), else of the source

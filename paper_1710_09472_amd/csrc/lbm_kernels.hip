@@ -31,14 +31,15 @@ static int env_int(const char *name, int dflt)
 }
 
 // Nodes per thread of the step kernel (measured on MI355X): 1 for FP32 and for D3V19,
-// 2 for 16-bit D2V9 except in the in-place step with solids (FP16 2048^2 disks in place:
-// 40.4 us with one node per thread, 41.8 us with two); halved until it divides nx.
-// LBM_STEP_VEC=1|2 overrides it.
-int step_vector_width(int lattice, int storage, int nx, bool inplace_solids)
+// 2 for 16-bit D2V9 except in the local phase of the in-place step with solids (FP16
+// 2048^2 disks in place: pull phase 33.0 us with one node per thread, 30.8 us with two;
+// local phase 46.4 us with one, 53.7 us with two); halved until it divides nx. The
+// layout and the bits are the same for either width. LBM_STEP_VEC=1|2 overrides it.
+int step_vector_width(int lattice, int storage, int nx, bool local_phase_solids)
 {
     static const int forced = env_int("LBM_STEP_VEC", 0);
     int v = forced;
-    if (v != 1 && v != 2) v = (storage != LBM_F32 && lattice == LBM_D2V9 && !inplace_solids) ? 2 : 1;
+    if (v != 1 && v != 2) v = (storage != LBM_F32 && lattice == LBM_D2V9 && !local_phase_solids) ? 2 : 1;
     while (v > 1 && nx % v) v >>= 1;
     return v;
 }
