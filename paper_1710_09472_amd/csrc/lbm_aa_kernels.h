@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_step_aa_local(StepArgs a, int ntx, F
     uint32_t h[V];
 #pragma unroll
     for (int i = 0; i < V; ++i) h[i] = SR ? sr_node((uint32_t)t.own + (uint32_t)i, a.sr_key) : 0u;
-    store_tile<LAT, ST, MASK, V, SR>(a.g, f, t, lk, o, h);
+    store_tile<LAT, ST, MASK, V, SR, true>(a.g, f, t, lk, o, h);
 }
 
 // Runtime flags -> template instances.

@@ -495,7 +495,11 @@ __device__ __forceinline__ void gather_tile(const Geometry &g, const typename Co
 // of the solid node x - e_q). There every value is loaded once from a per-lane address
 // (own slot or solid slot), so that no load waits for another; 16-bit states are below
 // 4 GiB, so one 32-bit byte offset from src reaches every slot. Waves without a bounced
-// link load node pairs with vector loads.
+// link load node pairs with vector loads. The per-lane loads go through the cache (not
+// non-temporal): the local phase then stores the bounced copies into the same solid-slot
+// lines, and the next pull phase finds them cached (measured on MI355X with the in-place
+// local phase's non-temporal bounced stores: FP16 2048^2 disks -11 % per step, FP16 Hall
+// duct -6 %, the paper's 3D Ohm sample in FP16 -6 %).
 template <int LAT, int ST, bool MASK, int V>
 __device__ __forceinline__ void gather_odd(const Geometry &g, const typename Codec<ST>::T *src, float inv_scale,
                                            const Tile &t, const typename LinkMask<LAT>::T *lk,
@@ -516,7 +520,7 @@ __device__ __forceinline__ void gather_odd(const Geometry &g, const typename Cod
 #pragma unroll
                 for (int i = 0; i < V; ++i) {
                     const unsigned off = (q != 0 && ((lk[i] >> q) & 1u)) ? row + pull_x<LAT, q, V>(r, i) : own + i;
-                    d[i][q] = Codec<ST>::dec(__builtin_nontemporal_load(at32(src, off)), inv_scale);
+                    d[i][q] = Codec<ST>::dec(*at32(src, off), inv_scale);
                 }
             });
             return;
@@ -738,7 +742,9 @@ __device__ __forceinline__ void collide(const Physics &p, const float *D, float 
 // f*_qbar(x), kept in slot q of that solid node. With the own-slot convention solid nodes
 // beside fluid ones in the wave store their own slots too (read by no pull).
 // With SR the codes are rounded stochastically with the node hashes h (sr_node).
-template <int LAT, int ST, bool MASK, int V, bool SR = false>
+// NT_BOUNCED: the bounced copies are non-temporal stores (the in-place local phase; in the
+// two-buffer step they measured slower: 2048^2 disks +3 %, the paper's 3D Ohm sample +8 %).
+template <int LAT, int ST, bool MASK, int V, bool SR = false, bool NT_BOUNCED = false>
 __device__ __forceinline__ void store_tile(const Geometry &g, typename Codec<ST>::T *__restrict__ dst, const Tile &t,
                                            const typename LinkMask<LAT>::T (&lk)[V], const float (&o)[V][Lat<LAT>::Q],
                                            const uint32_t *h = nullptr)
@@ -789,9 +795,13 @@ __device__ __forceinline__ void store_tile(const Geometry &g, typename Codec<ST>
                 T *row = dst + pull_row<LAT, q>(g, t, r);
 #pragma unroll
                 for (int i = 0; i < V; ++i)
-                    if (fluid[i] && ((lk[i] >> q) & 1u))
-                        *at32(row, pull_x<LAT, q, V>(r, i)) =
-                            enc_store<ST, SR>(o[i][L::opp[q]], SR ? h[i] : 0u, L::opp[q]);
+                    if (fluid[i] && ((lk[i] >> q) & 1u)) {
+                        const T c = enc_store<ST, SR>(o[i][L::opp[q]], SR ? h[i] : 0u, L::opp[q]);
+                        if constexpr (NT_BOUNCED)
+                            __builtin_nontemporal_store(c, at32(row, pull_x<LAT, q, V>(r, i)));
+                        else
+                            *at32(row, pull_x<LAT, q, V>(r, i)) = c;
+                    }
             }
         });
     }
